@@ -1,0 +1,95 @@
+"""Seeded synthetic inputs shared by the oracle tests and the HIP path.
+
+This module draws random numbers and shapes images; it holds none of the
+projection's arithmetic.  Every generator takes an explicit seed and uses
+numpy's PCG64 behind SeedSequence, so the oracle and the GPU path see the same
+bytes.
+
+Workload shapes (the paper's test data -- a blurred, noisy test image and a
+quantum-dot fluorescence movie, Sec. 4.1 -- are not available; these stand in):
+
+* noise_blob: i.i.d. N(0,1) residual plus one Gaussian blob (amplitude 4,
+  sigma 3 px) at the image centre ((H-1)/2, (W-1)/2).
+* emitters: residual of a fluorescence frame following the fluctuation model of
+  Sec. 2.4: n_e point emitters at uniform pixel positions with Poisson(50)
+  photon counts, blurred by a Gaussian PSF (sigma 1.5 px, truncated at 4 sigma,
+  zero outside the image), minus the blurred mean (50 per emitter), divided by
+  its population standard deviation.  Pixels far from every emitter stay 0.
+"""
+import numpy as np
+from scipy.ndimage import gaussian_filter
+
+
+def rng_for(seed):
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+
+
+def noise_blob(H=64, W=64, seed=0, amp=4.0, sigma=3.0):
+    rng = rng_for(seed)
+    x = rng.standard_normal((H, W))
+    r = np.arange(H)[:, None] - (H - 1) / 2.0
+    c = np.arange(W)[None, :] - (W - 1) / 2.0
+    x = x + amp * np.exp(-(r * r + c * c) / (2.0 * sigma * sigma))
+    return x.astype(np.float64)
+
+
+def emitters(H, W, n_e=None, seed=0, rng=None, mean_count=50.0, psf_sigma=1.5):
+    if rng is None:
+        rng = rng_for(seed)
+    if n_e is None:
+        n_e = int(round(H * W / 1300.0))
+    rows = rng.integers(0, H, size=n_e)
+    cols = rng.integers(0, W, size=n_e)
+    counts = rng.poisson(mean_count, size=n_e).astype(np.float64)
+    E = np.zeros((H, W))
+    np.add.at(E, (rows, cols), counts)
+    M = np.zeros((H, W))
+    np.add.at(M, (rows, cols), mean_count)
+    R = gaussian_filter(E - M, psf_sigma, mode="constant", truncate=4.0)
+    sd = R.std()
+    if sd == 0.0:
+        return R
+    return (R / sd).astype(np.float64)
+
+
+def gaussian(H, W, seed=0, scale=1.0):
+    return scale * rng_for(seed).standard_normal((H, W))
+
+
+BATCH_SIDES = (128, 256, 384, 512, 768)
+
+
+def batch_images(n=64, seed=0, sides=BATCH_SIDES):
+    """n emitter images with sides drawn uniformly from `sides`, 1 emitter per
+    1300 px^2, each from its own spawned seed sequence."""
+    ss = np.random.SeedSequence(seed)
+    pick = np.random.Generator(np.random.PCG64(ss))
+    chosen = pick.choice(np.asarray(sides), size=n)
+    children = ss.spawn(n)
+    out = []
+    for s, child in zip(chosen, children):
+        rng = np.random.Generator(np.random.PCG64(child))
+        out.append(emitters(int(s), int(s), rng=rng))
+    return out
+
+
+def serve_trace(n, rate=200.0, seed=0, lo=256, hi=1024):
+    """Poisson arrivals: (arrival_times_s, sides, images_rng_children).
+
+    Inter-arrival gaps ~ Exp(1/rate); side = round(exp(U(ln lo, ln hi)))."""
+    ss = np.random.SeedSequence(seed)
+    rng = np.random.Generator(np.random.PCG64(ss))
+    gaps = rng.exponential(1.0 / rate, size=n)
+    t = np.cumsum(gaps)
+    sides = np.rint(np.exp(rng.uniform(np.log(lo), np.log(hi), size=n))).astype(int)
+    return t, sides, ss.spawn(n)
+
+
+def serve_image(side, child):
+    rng = np.random.Generator(np.random.PCG64(child))
+    return emitters(int(side), int(side), rng=rng)
+
+
+def serve_sides(side):
+    """Window sides 1..max(8, side // 64)."""
+    return list(range(1, max(8, int(side) // 64) + 1))
