@@ -1,0 +1,164 @@
+/*
+ * smre.h -- C ABI of the MI355X (gfx950) SMRE projection library.
+ *
+ * What it computes (paper: "Parallel Statistical Multi-resolution Estimation",
+ * arXiv 1503.03492):
+ *   - the Euclidean projection of a residual image x0 onto
+ *       { v : sum_{i in S} v_i^2 <= r2_S  for every square window S }
+ *     (the feasible set tau_G of Sec. 2, Eqs. (tau_s), (tau_G); the projection
+ *     P_G of Sec. 2.2), by Dykstra's cyclic projection algorithm (Sec. 2.3,
+ *     Algorithm 2, single-set projection Eq. (dykstra:if)).  The family holds
+ *     every s x s square lying fully inside the image, for each configured
+ *     side s.  The paper writes the constraint as c_s * sum <= 1; here the
+ *     bound r2_S = 1/c_s is passed directly.
+ *   - the paper's incomplete Dykstra (ICD) of Sec. 3.2: squares of side 2^k
+ *     (k <= K) on lattices shifted diagonally by 2^i, projected blockwise.
+ *
+ * Conventions.
+ *   - Every function returns an int status (smre_status); no exception or
+ *     abort crosses this boundary.  SMRE_NOT_CONVERGED is a warning: the
+ *     result has been written.
+ *   - Image buffers are row-major with a row stride `ld` (elements, ld >= W).
+ *     `x` arguments of the projection calls are DEVICE pointers, updated in
+ *     place; the caller owns them.  Bounds, sides and reports are HOST memory.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on
+ *     it in order.  The projection calls return after the result is complete
+ *     (the convergence test needs the host), so `x` may be read right away.
+ *   - A context (smre_ctx) is bound to one device; it caches workspaces and
+ *     tuning results.  It is not thread-safe: use one per host thread.
+ */
+#ifndef SMRE_H
+#define SMRE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SMRE_OK = 0,
+  SMRE_NOT_CONVERGED = 1, /* warning: sweep cap reached, result written        */
+  SMRE_PENDING = 2,       /* serving: ticket not finished yet                  */
+  SMRE_EINVAL = -1,       /* invalid argument                                  */
+  SMRE_ENONFINITE = -2,   /* NaN or Inf in the input image or the bounds       */
+  SMRE_ENOMEM = -3,       /* device allocation failed / workspace too small    */
+  SMRE_ETOOBIG = -4,      /* request can never fit the memory budget           */
+  SMRE_EBUSY = -5,        /* queue full                                        */
+  SMRE_EDEVICE = -6,      /* HIP runtime error                                 */
+  SMRE_ECANCELLED = -7,   /* server shut down before the ticket finished       */
+  SMRE_EUNKNOWN_TICKET = -8
+} smre_status;
+
+typedef enum { SMRE_F32 = 0, SMRE_F64 = 1 } smre_dtype;       /* dtype of x        */
+typedef enum { SMRE_INC_SAME = 0, SMRE_INC_BF16 = 1 } smre_inc; /* increment storage */
+typedef enum { SMRE_TOL_MAXABS = 0, SMRE_TOL_MEANABS = 1 } smre_tolmode;
+
+typedef struct smre_ctx smre_ctx;
+
+/* Parameters of the full projection.
+ *   sides[n_sides]    distinct window sides, 1 <= s <= min(H, W), s <= 32
+ *   radius2[n_sides]  bound r2_s of the sum of squares over a window of side s
+ *                     (finite, > 0)
+ *   tol               stop after the first checked sweep whose largest
+ *                     pixel change max_i |x_i - x_prev_i| (FP64) is < tol;
+ *                     tol <= 0 runs exactly max_sweeps sweeps
+ *   max_sweeps        sweep cap (>= 1)
+ *   check_every       test convergence every this many sweeps (>= 1)
+ *   region            side R of the anchor regions of the sweep order
+ *                     (0 = choose; else 8, 16 or 32 with R >= max side - 1)
+ *   inc               increment storage (FP32 x only for SMRE_INC_BF16)
+ *   kahan             FP32: compensated per-lane window sums (0/1)
+ *   guard_rel         FP32: windows with |n - r2| <= guard_rel * r2 are
+ *                     re-summed in FP64 before the threshold test (0 = off)
+ *
+ * Sweep order.  Dykstra's limit does not depend on the cyclic order of the
+ * sets (Sec. 2.3), so the library uses an order that needs no ordering
+ * between overlapping sets inside a kernel: the anchor (top-left) plane is cut
+ * into R x R regions coloured 2 (p mod 2) + (q mod 2); colour by colour, each
+ * region visits its windows side by side (descending), offset (a, b) by offset
+ * in raster order, where offset (a, b) selects the disjoint tiling of anchors
+ * congruent to (a, b) mod s.  Regions of one colour touch disjoint pixels.
+ */
+typedef struct {
+  int32_t n_sides;
+  const int32_t* sides;
+  const double* radius2;
+  double tol;
+  int32_t max_sweeps;
+  int32_t check_every;
+  int32_t region;
+  int32_t inc;
+  int32_t kahan;
+  int32_t reserved0;
+  double guard_rel;
+} smre_params;
+
+typedef struct {
+  int32_t sweeps;              /* sweeps run (the converged sweep if converged) */
+  int32_t converged;           /* 1 if the tolerance was met                   */
+  int32_t region;              /* region side R used                           */
+  int32_t inner_sweeps;        /* ICD: total inner sweeps over all blocks       */
+  double last_delta;           /* last measured max |x - x_prev| (FP64)         */
+  double max_violation;        /* max_S sum_S x^2 / r2_S - 1 at exit (FP64)     */
+  double elapsed_ms;           /* wall time of the call, device-side events     */
+  double kernel_ms;            /* sum of sweep-kernel durations (timing on)     */
+  double bytes_moved;          /* algorithmic HBM bytes of the sweeps           */
+  double window_projections;   /* single-window projections performed           */
+  int64_t kernel_launches;     /* sweep-kernel launches timed                   */
+} smre_report;
+
+const char* smre_status_string(int status);
+
+/* Context bound to `device` (a HIP device ordinal). */
+int smre_ctx_create(int device, smre_ctx** out);
+void smre_ctx_destroy(smre_ctx* ctx);
+/* Record HIP events around every sweep kernel (reported in smre_report). */
+int smre_ctx_set_timing(smre_ctx* ctx, int on);
+
+/* Window bounds on the host: chi-square(s*s degrees of freedom) p-quantile
+ * for each side, i.e. the bound that i.i.d. N(0,1) noise meets with
+ * probability p on one window. */
+int smre_chi2_bounds(const int32_t* sides, int32_t n, double p, double* radius2_out);
+/* The paper's weights (Sec. 2.1): r2 = 1/c_s = (q_alpha sigma_s + mu_s)^4,
+ * mu_s = (|s| - 1/2)^(1/4), sigma_s^2 = 1/(8 sqrt|s|), |s| = side^2. */
+int smre_paper_bounds(const int32_t* sides, int32_t n, double q_alpha, double* radius2_out);
+
+/* Bytes of device workspace smre_dykstra_project needs for this problem. */
+int smre_workspace_size(smre_dtype dtype, int64_t H, int64_t W, const smre_params* p,
+                        size_t* bytes);
+
+/* Full Dykstra projection of x (device, H x W, stride ld), in place.
+ * workspace: device memory of at least smre_workspace_size bytes, or NULL
+ * (the context allocates and caches it).  report may be NULL.
+ * Returns SMRE_OK, SMRE_NOT_CONVERGED, or an error. */
+int smre_dykstra_project(smre_ctx* ctx, smre_dtype dtype, void* x, int64_t H, int64_t W,
+                         int64_t ld, const smre_params* p, void* workspace, size_t ws_bytes,
+                         void* stream, smre_report* report);
+
+/* Incomplete Dykstra (Sec. 3.2), in place on x (device).
+ *   K             block side 2^K (0 <= K <= 5); levels k = 0..K
+ *   radius2[K+1]  bound of a square of side 2^k
+ *   tol, tolmode  block stopping rule after each inner sweep:
+ *                 MAXABS: max |dx| < tol; MEANABS: sum |dx| <= tol * block pixels
+ *   max_inner     cap on inner sweeps per block (>= 1; one always runs)
+ *   num_phases    phases i = 0..num_phases-1 (1..K+1; the paper's family: K+1)
+ * Phase i: blocks on the lattice shifted by 2^i mod 2^K on both axes; a block
+ * projects onto its squares of side 2^k, k = K down to i, with increments
+ * zeroed at the start of the phase. */
+int smre_dykstra_incomplete(smre_ctx* ctx, smre_dtype dtype, void* x, int64_t H, int64_t W,
+                            int64_t ld, int32_t K, const double* radius2, double tol,
+                            int32_t tolmode, int32_t max_inner, int32_t num_phases, void* stream,
+                            smre_report* report);
+
+/* FP64 feasibility of x (device): *out = max_S sum_S x^2 / r2_S - 1 over all
+ * windows of the given sides (<= 0 means every constraint holds). */
+int smre_max_violation(smre_ctx* ctx, smre_dtype dtype, const void* x, int64_t H, int64_t W,
+                       int64_t ld, int32_t n_sides, const int32_t* sides, const double* radius2,
+                       void* stream, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SMRE_H */

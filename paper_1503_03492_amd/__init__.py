@@ -1,0 +1,243 @@
+"""Python binding of libsmre.so (the MI355X SMRE projection library).
+
+Argument marshalling only: every step of the projection runs in the HIP
+kernels behind the C ABI declared in include/smre.h.  PyTorch supplies device
+memory and the current stream.  There is no CPU fallback: if the library is
+missing, importing this package raises.
+"""
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsmre.so")
+
+OK = 0
+NOT_CONVERGED = 1
+PENDING = 2
+F32, F64 = 0, 1
+INC_SAME, INC_BF16 = 0, 1
+TOL_MAXABS, TOL_MEANABS = 0, 1
+
+
+class SmreError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {status_string(code)} ({code})")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n_sides", ctypes.c_int32), ("sides", ctypes.POINTER(ctypes.c_int32)),
+                ("radius2", ctypes.POINTER(ctypes.c_double)), ("tol", ctypes.c_double),
+                ("max_sweeps", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("region", ctypes.c_int32), ("inc", ctypes.c_int32), ("kahan", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("guard_rel", ctypes.c_double)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("region", ctypes.c_int32), ("inner_sweeps", ctypes.c_int32),
+                ("last_delta", ctypes.c_double), ("max_violation", ctypes.c_double),
+                ("elapsed_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double),
+                ("bytes_moved", ctypes.c_double), ("window_projections", ctypes.c_double),
+                ("kernel_launches", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(or python -m paper_1503_03492_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    ip, dp = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)
+    L.smre_status_string.argtypes = [ctypes.c_int]
+    L.smre_status_string.restype = ctypes.c_char_p
+    L.smre_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
+    L.smre_ctx_destroy.argtypes = [vp]
+    L.smre_ctx_destroy.restype = None
+    L.smre_ctx_set_timing.argtypes = [vp, ctypes.c_int]
+    L.smre_chi2_bounds.argtypes = [ip, i32, dbl, dp]
+    L.smre_paper_bounds.argtypes = [ip, i32, dbl, dp]
+    L.smre_workspace_size.argtypes = [ctypes.c_int, i64, i64, ctypes.POINTER(Params),
+                                      ctypes.POINTER(ctypes.c_size_t)]
+    L.smre_dykstra_project.argtypes = [vp, ctypes.c_int, vp, i64, i64, i64,
+                                       ctypes.POINTER(Params), vp, ctypes.c_size_t, vp,
+                                       ctypes.POINTER(Report)]
+    L.smre_dykstra_incomplete.argtypes = [vp, ctypes.c_int, vp, i64, i64, i64, i32, dp, dbl,
+                                          i32, i32, i32, vp, ctypes.POINTER(Report)]
+    L.smre_max_violation.argtypes = [vp, ctypes.c_int, vp, i64, i64, i64, i32, ip, dp, vp, dp]
+    return L
+
+
+_lib = _load()
+
+EXPORTS = ["smre_status_string", "smre_ctx_create", "smre_ctx_destroy", "smre_ctx_set_timing",
+           "smre_chi2_bounds", "smre_paper_bounds", "smre_workspace_size",
+           "smre_dykstra_project", "smre_dykstra_incomplete", "smre_max_violation"]
+
+
+def lib():
+    return _lib
+
+
+def status_string(code):
+    return _lib.smre_status_string(int(code)).decode()
+
+
+def _check(code, what, allow=(OK,)):
+    if code not in allow:
+        raise SmreError(code, what)
+    return code
+
+
+def _ivec(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _dvec(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def chi2_bounds(sides, p=0.9):
+    s, sp = _ivec(sides)
+    out = np.empty(len(s))
+    _check(_lib.smre_chi2_bounds(sp, len(s), float(p), _dvec(out)[1]), "smre_chi2_bounds")
+    return out
+
+
+def paper_bounds(sides, q_alpha):
+    s, sp = _ivec(sides)
+    out = np.empty(len(s))
+    _check(_lib.smre_paper_bounds(sp, len(s), float(q_alpha), _dvec(out)[1]),
+           "smre_paper_bounds")
+    return out
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise TypeError("x must be float32 or float64")
+
+
+def _image(x):
+    import torch
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError("x must be a CUDA (HIP) tensor")
+    if x.dim() != 2 or x.stride(1) != 1:
+        raise ValueError("x must be 2-D with unit column stride")
+    return x.shape[0], x.shape[1], x.stride(0)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+@dataclass
+class ProjectOptions:
+    tol: float = 1e-5
+    max_sweeps: int = 5000
+    check_every: int = 1
+    region: int = 0
+    inc: int = INC_SAME
+    kahan: bool = True
+    guard_rel: float = 1e-5
+
+
+class Context:
+    """One per device and host thread; caches the workspace between calls."""
+
+    def __init__(self, device=0):
+        h = ctypes.c_void_p()
+        _check(_lib.smre_ctx_create(int(device), ctypes.byref(h)), "smre_ctx_create")
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if self._h:
+            _lib.smre_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_timing(self, on):
+        _check(_lib.smre_ctx_set_timing(self._h, 1 if on else 0), "smre_ctx_set_timing")
+
+    @staticmethod
+    def _params(sides, radius2, o):
+        s, sp = _ivec(sides)
+        r, rp = _dvec(radius2)
+        if len(s) != len(r):
+            raise ValueError("sides and radius2 differ in length")
+        p = Params(len(s), sp, rp, float(o.tol), int(o.max_sweeps), int(o.check_every),
+                   int(o.region), int(o.inc), 1 if o.kahan else 0, 0, float(o.guard_rel))
+        return p, (s, r)
+
+    def workspace_size(self, dtype, H, W, sides, radius2, opts=None):
+        p, keep = self._params(sides, radius2, opts or ProjectOptions())
+        n = ctypes.c_size_t()
+        _check(_lib.smre_workspace_size(int(dtype), H, W, ctypes.byref(p), ctypes.byref(n)),
+               "smre_workspace_size")
+        return n.value
+
+    def project(self, x, sides, radius2, opts=None, workspace=None, stream=None, **kw):
+        """Full Dykstra projection of x (2-D CUDA tensor), in place.  Returns
+        (status, report dict); status is OK or NOT_CONVERGED."""
+        o = opts or ProjectOptions()
+        for k, v in kw.items():
+            setattr(o, k, v)
+        H, W, ld = _image(x)
+        p, keep = self._params(sides, radius2, o)
+        rep = Report()
+        ws_ptr, ws_bytes = None, 0
+        if workspace is not None:
+            ws_ptr, ws_bytes = ctypes.c_void_p(workspace.data_ptr()), workspace.numel() * \
+                workspace.element_size()
+        rc = _lib.smre_dykstra_project(self._h, _dtype_code(x), ctypes.c_void_p(x.data_ptr()), H,
+                                       W, ld, ctypes.byref(p), ws_ptr, ws_bytes,
+                                       _stream(stream), ctypes.byref(rep))
+        _check(rc, "smre_dykstra_project", allow=(OK, NOT_CONVERGED))
+        return rc, rep.as_dict()
+
+    def incomplete(self, x, K, radius2, tol=1e-3, mode=TOL_MEANABS, max_inner=10000,
+                   num_phases=None, stream=None):
+        """Incomplete Dykstra of x (2-D CUDA tensor), in place; returns report dict."""
+        H, W, ld = _image(x)
+        r, rp = _dvec(radius2)
+        if len(r) != K + 1:
+            raise ValueError("radius2 needs K+1 entries")
+        if num_phases is None:
+            num_phases = K + 1
+        rep = Report()
+        rc = _lib.smre_dykstra_incomplete(self._h, _dtype_code(x), ctypes.c_void_p(x.data_ptr()),
+                                          H, W, ld, int(K), rp, float(tol), int(mode),
+                                          int(max_inner), int(num_phases), _stream(stream),
+                                          ctypes.byref(rep))
+        _check(rc, "smre_dykstra_incomplete")
+        return rep.as_dict()
+
+    def max_violation(self, x, sides, radius2, stream=None):
+        H, W, ld = _image(x)
+        s, sp = _ivec(sides)
+        r, rp = _dvec(radius2)
+        out = ctypes.c_double()
+        _check(_lib.smre_max_violation(self._h, _dtype_code(x), ctypes.c_void_p(x.data_ptr()), H,
+                                       W, ld, len(s), sp, rp, _stream(stream), ctypes.byref(out)),
+               "smre_max_violation")
+        return out.value

@@ -1,0 +1,174 @@
+// icd.hpp -- incomplete Dykstra (ICD) phase kernel for gfx950.
+//
+// Sec. 3.2 restricts the family to squares of side 2^k (k <= K) on lattices
+// shifted diagonally by 2^i and projects phase by phase: phase i works on
+// blocks of side 2^K on the lattice offset by o_i = 2^i mod 2^K; a block runs
+// Dykstra over its squares of side 2^K, 2^(K-1), ..., 2^i with increments
+// zeroed at the phase start, until the block converges.  Blocks of a phase
+// are disjoint, so one wave per block runs them all in parallel.
+//
+// Layout inside a wave: the block's 4^K pixels in Morton (Z) order, NPL =
+// max(1, 4^K / 64) consecutive Morton indices per lane.  A square of side 2^k
+// is then an aligned run of 4^k Morton indices: inside one lane when
+// 4^k <= NPL, else an aligned group of 4^k / NPL lanes, reduced with DPP and
+// permlane swaps.  Pixels, increments and sums stay in registers; HBM sees
+// one read and one write of x per phase.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace smre {
+
+__device__ __forceinline__ int morton_x(int m) {
+  int x = 0;
+#pragma unroll
+  for (int b = 0; b < 6; ++b) x |= ((m >> (2 * b)) & 1) << b;
+  return x;
+}
+__device__ __forceinline__ int morton_y(int m) { return morton_x(m >> 1); }
+
+// t = sqrt(r2 / n) if n > r2 else 1, in the precision of the image.
+template <typename T> __device__ __forceinline__ T ball_scale(T n, T r2) {
+  if constexpr (sizeof(T) == 8) return n > r2 ? __builtin_sqrt(r2 / n) : T(1);
+  else return n > r2 ? __builtin_sqrtf(r2 / n) : T(1);
+}
+
+template <typename T> __device__ __forceinline__ T wave_max(T v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+struct IcdArgs {
+  void* x;
+  int64_t ld;
+  int32_t H, W;
+  int32_t phase;
+  int32_t mode;       // 0: max |dx| < tol, 1: sum |dx| <= tol * block pixels
+  int32_t max_inner;
+  int32_t pad;
+  double tol;
+  double r2[6];
+  int* inner_count;   // total inner sweeps (device)
+};
+
+template <typename T, int K>
+__global__ __launch_bounds__(64) void icd_phase(IcdArgs a) {
+  constexpr int B = 1 << K;
+  constexpr int NPX = B * B;
+  constexpr int NPL = NPX >= 64 ? NPX / 64 : 1;
+  const int lane = threadIdx.x;
+  const int i = a.phase;
+  const int o = (1 << i) & (B - 1);
+  const int by = (o > 0 ? o - B : 0) + (int)blockIdx.y * B;
+  const int bx = (o > 0 ? o - B : 0) + (int)blockIdx.x * B;
+  T* xg = (T*)a.x;
+
+  T x[NPL];
+  bool inimg[NPL];
+  int gy[NPL], gx[NPL];
+  int npix = 0;
+#pragma unroll
+  for (int e = 0; e < NPL; ++e) {
+    const int m = lane * NPL + e;
+    gy[e] = by + morton_y(m);
+    gx[e] = bx + morton_x(m);
+    inimg[e] = m < NPX && gy[e] >= 0 && gx[e] >= 0 && gy[e] < a.H && gx[e] < a.W;
+    x[e] = inimg[e] ? xg[(int64_t)gy[e] * a.ld + gx[e]] : T(0);
+    npix += inimg[e];
+  }
+  // pixels of the block inside the image (for the mean-abs rule)
+  float npf = (float)npix;
+  npf = group_sum<64>(npf);
+
+  // active[k][e]: the level-k square holding pixel e lies inside the image.
+  bool active[K + 1][NPL];
+#pragma unroll
+  for (int k = 0; k <= K; ++k)
+#pragma unroll
+    for (int e = 0; e < NPL; ++e) {
+      const int L = 1 << k;
+      const int sy = gy[e] - ((gy[e] - by) & (L - 1));
+      const int sx = gx[e] - ((gx[e] - bx) & (L - 1));
+      active[k][e] = (lane * NPL + e) < NPX && sy >= 0 && sx >= 0 && sy + L <= a.H &&
+                     sx + L <= a.W;
+    }
+
+  T q[K + 1][NPL];
+#pragma unroll
+  for (int k = 0; k <= K; ++k)
+#pragma unroll
+    for (int e = 0; e < NPL; ++e) q[k][e] = T(0);
+
+  int it = 0;
+  while (true) {
+    double dsum = 0.0;
+    T dmax = T(0);
+#pragma unroll
+    for (int k = K; k >= 0; --k) {
+      if (k < i) break;
+      const T r2 = (T)a.r2[k];
+      T y[NPL];
+#pragma unroll
+      for (int e = 0; e < NPL; ++e) y[e] = x[e] - q[k][e];
+      T t[NPL];
+      const int sq = 1 << (2 * k);  // pixels per square
+      if (sq <= NPL) {
+        // squares inside one lane: consecutive runs of sq Morton indices
+#pragma unroll
+        for (int e0 = 0; e0 < NPL; e0 += 1) {
+          if (e0 % sq) continue;
+          T n = T(0);
+#pragma unroll
+          for (int e = 0; e < NPL; ++e)
+            if (e >= e0 && e < e0 + sq) n += y[e] * y[e];
+          const T tt = ball_scale(n, r2);
+#pragma unroll
+          for (int e = 0; e < NPL; ++e)
+            if (e >= e0 && e < e0 + sq) t[e] = tt;
+        }
+      } else {
+        T part = T(0);
+#pragma unroll
+        for (int e = 0; e < NPL; ++e) part += y[e] * y[e];
+        T n;
+        switch (sq / NPL) {
+          case 2: n = group_sum<2>(part); break;
+          case 4: n = group_sum<4>(part); break;
+          case 8: n = group_sum<8>(part); break;
+          case 16: n = group_sum<16>(part); break;
+          case 32: n = group_sum<32>(part); break;
+          default: n = group_sum<64>(part); break;
+        }
+        const T tt = ball_scale(n, r2);
+#pragma unroll
+        for (int e = 0; e < NPL; ++e) t[e] = tt;
+      }
+#pragma unroll
+      for (int e = 0; e < NPL; ++e) {
+        if (active[k][e]) {
+          const T xn = t[e] * y[e];
+          q[k][e] = xn - y[e];
+          const T d = fabs(x[e] - xn);
+          dsum += (double)d;
+          dmax = fmax(dmax, d);
+          x[e] = xn;
+        }
+      }
+    }
+    ++it;
+    bool stop;
+    if (a.mode == 1) {
+      const double s = group_sum<64>(dsum);
+      stop = s <= a.tol * (double)npf;
+    } else {
+      stop = (double)wave_max(dmax) < a.tol;
+    }
+    if (stop || it >= a.max_inner) break;
+  }
+#pragma unroll
+  for (int e = 0; e < NPL; ++e)
+    if (inimg[e]) xg[(int64_t)gy[e] * a.ld + gx[e]] = x[e];
+  if (lane == 0) atomicAdd(a.inner_count, it);
+}
+
+}  // namespace smre
