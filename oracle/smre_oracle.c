@@ -228,8 +228,10 @@ static void project_tiling_part(double* x, double* inc, int64_t H, int64_t W, in
  *
  * ORDER_REGION(R): the anchor plane is cut into R x R regions; region (p, q)
  * gets colour 2 (p mod 2) + (q mod 2).  For colour 0, 1, 2, 3 in turn, for
- * every region of that colour, for each side descending, for each offset (a, b)
- * raster, the windows of tiling (s, a, b) anchored in the region.  With
+ * every region of that colour, for each side descending, for each offset
+ * (a', b') in raster order counted from the region origin (p R, q R), the
+ * windows anchored at (p R + a' + s i, q R + b' + s j) inside the region --
+ * the part of tiling ((p R + a') mod s, (q R + b') mod s) in the region.  With
  * R >= smax - 1 two regions of one colour touch disjoint pixels, so the order
  * of regions within a colour is immaterial as well.
  */
@@ -255,8 +257,10 @@ static void sweep(double* x, double* incs, int64_t H, int64_t W, const side_tabl
       for (int64_t q = color & 1; q < nrx; q += 2)
         for (int k = 0; k < st->n; ++k) {
           int32_t s = st->side[k];
-          for (int32_t a = 0; a < s; ++a)
-            for (int32_t b = 0; b < s; ++b) {
+          for (int32_t ap = 0; ap < s; ++ap)
+            for (int32_t bp = 0; bp < s; ++bp) {
+              /* offsets (ap, bp) count from the region origin */
+              int32_t a = (int32_t)((p * R + ap) % s), b = (int32_t)((q * R + bp) % s);
               double* inc = incs + (st->tbase[k] + (int64_t)a * s + b) * HW;
               project_tiling_part(x, inc, H, W, s, a, b, st->r2[k], p * R, p * R + R, q * R,
                                   q * R + R, ybuf);

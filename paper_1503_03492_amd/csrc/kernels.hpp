@@ -6,23 +6,32 @@
 // regions of one colour; with R >= smax - 1 their pixel footprints
 // (R + smax - 1)^2 are disjoint, so the launch needs no ordering between
 // workgroups.  Inside a region the workgroup visits every window anchored in
-// it, side by side (descending), tiling offset by tiling offset; windows of one
-// tiling are disjoint (Sec. 2.3), so a step projects all of them at once.
+// it: side by side (descending), then tiling offset (a', b') relative to the
+// region origin in raster order; the windows of one offset are disjoint
+// (Sec. 2.3), so a step projects all of them at once.
 //
 // Workgroup = 2 waves:
 //   wave 0 (consumer) keeps the region's x footprint in LDS for the whole
 //     phase and runs the steps: y = x + I, n = sum y^2 per window (lanes of a
 //     window reduce with DPP / permlane swaps), t = sqrt(r2/n) if n > r2,
-//     x' = t y, I' = y - x'.  I' is stored straight to HBM.
-//   wave 1 (producer) streams the region's increments -- one contiguous
+//     x' = t y, I' = y - x'.  I' goes straight to HBM.
+//   wave 1 (producer) streams the region's increments -- one contiguous byte
 //     range of the increment buffer per region and sweep -- through a ring of
 //     1 KiB pages in LDS, several loads in flight, gated by the consumer's
-//     progress.  The two waves synchronise through two LDS counters only.
+//     progress.  The first pages of the ring are mirrored after its end so a
+//     round's chunk is always a linear LDS range.  The two waves synchronise
+//     through two LDS counters only.
 //
-// Increment layout: for each region (raster order), its steps in visiting
-// order; inside a step, rounds of up to 64/G windows; inside a round, slots
-// (u, v) in order; inside a slot, the active lanes' elements contiguously.
-// Every load and store of a slot is therefore one dense run of elements.
+// With one consumer wave per SIMD every instruction costs an issue slot, so
+// the step is written for instruction count: a lane serves a fixed window
+// slot per side, so its LDS pixel addresses are one base plus compile-time
+// immediates; increments are laid out window-major inside a round so the
+// per-slot offsets are immediates too; stores of masked lanes are dropped by
+// the buffer unit (out-of-range offset) instead of branching.
+//
+// Increment layout: per region (raster order), its steps in visiting order;
+// per step, rounds of up to BR x BC windows; per round, the valid windows in
+// row-major order, S^2 elements each, ordered by slot (u, v) then lane.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -31,8 +40,7 @@
 namespace smre {
 
 constexpr int kPage = 1024;            // bytes per prefetch page (64 lanes x 16 B)
-constexpr int kSlots = 32;             // pages in the LDS ring
-constexpr int kRing = kPage * kSlots;  // ring bytes
+constexpr int kSlots = 16;             // pages in the LDS ring (power of two)
 constexpr int kMaxSides = 32;
 constexpr int kPrefetch = 8;           // producer loads in flight
 
@@ -46,48 +54,139 @@ __device__ __forceinline__ bf16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
+// Increment element I/O: read from the LDS ring, write to HBM through a raw
+// buffer resource.  A store whose byte offset lies past the resource's
+// num_records is dropped by the hardware, which masks lanes without branches.
+constexpr uint32_t kDropOffset = 0x80000000u;
+constexpr int kRsrcWord3 = 0x00020000;
+
 template <typename TQ, typename TC> struct QStore;
 template <> struct QStore<float, float> {
   static __device__ __forceinline__ float get(const unsigned char* p) { return *(const float*)p; }
-  static __device__ __forceinline__ void put(float* q, float v) { *q = v; }
+  static __device__ __forceinline__ void put(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
+                                             float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
+  }
 };
 template <> struct QStore<double, double> {
   static __device__ __forceinline__ double get(const unsigned char* p) { return *(const double*)p; }
-  static __device__ __forceinline__ void put(double* q, double v) { *q = v; }
+  static __device__ __forceinline__ void put(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
+                                             double v) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+  }
 };
 template <> struct QStore<bf16_t, float> {
   static __device__ __forceinline__ float get(const unsigned char* p) {
     return bf2f(*(const bf16_t*)p);
   }
-  static __device__ __forceinline__ void put(bf16_t* q, float v) { *q = f2bf(v); }
+  static __device__ __forceinline__ void put(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
+                                             float v) {
+    __builtin_amdgcn_raw_buffer_store_b16(f2bf(v), r, voff, soff, 0);
+  }
 };
 
 // ---------------------------------------------------------------- lane patterns
-// A window of side S is served by G = GR x GC lanes: lane (jr, jc) holds the
-// pixels (jr + u GR, jc + v GC), u < U, v < V.  Chosen per (R, S) by a cost
-// model of rounds x (round overhead + elements per lane + reduction steps).
+// For side S in a region of side R, a window is served by G = GR x GC lanes
+// (lane (jr, jc) holds pixels (jr + u GR, jc + v GC), u < U, v < V) and a
+// round covers a block of BR x BC window slots (G BR BC = 64).  Picked per
+// (R, S) by counting issued instructions per step: rounds x (per-round
+// overhead + elements per lane + reduction steps).
 struct Pattern {
-  int gr, gc;
+  int gr, gc, br, bc;
 };
 __host__ __device__ constexpr Pattern pattern(int R, int S) {
   if (R == 8) {
-    constexpr Pattern t[10] = {{1, 1}, {1, 1}, {2, 2}, {1, 4}, {4, 4}, {2, 8},
-                               {2, 8}, {4, 8}, {8, 8}, {4, 16}};
+    constexpr Pattern t[10] = {{1, 1, 8, 8}, {1, 1, 8, 8}, {2, 2, 4, 4}, {2, 2, 4, 4},
+                               {4, 4, 2, 2}, {4, 4, 2, 2}, {4, 4, 2, 2}, {4, 4, 2, 2},
+                               {8, 8, 1, 1}, {8, 8, 1, 1}};
     return t[S];
   }
   if (R == 16) {
-    constexpr Pattern t[18] = {{1, 1}, {1, 1}, {1, 1},  {1, 2},  {1, 4},  {2, 2},
-                               {2, 2}, {1, 8}, {2, 8},  {1, 16}, {4, 4},  {4, 4},
-                               {2, 16}, {2, 16}, {2, 16}, {4, 16}, {4, 16}, {2, 32}};
+    constexpr Pattern t[18] = {{1, 1, 8, 8}, {1, 1, 8, 8}, {1, 1, 8, 8}, {1, 1, 8, 8},
+                               {2, 2, 4, 4}, {2, 2, 4, 4}, {2, 2, 4, 4}, {4, 4, 2, 2},
+                               {4, 4, 2, 2}, {4, 4, 2, 2}, {4, 4, 2, 2}, {4, 4, 2, 2},
+                               {4, 4, 2, 2}, {8, 8, 1, 1}, {8, 8, 1, 1}, {8, 8, 1, 1},
+                               {8, 8, 1, 1}, {8, 8, 1, 1}};
     return t[S];
   }
-  constexpr Pattern t[34] = {{1, 1},  {1, 1},  {1, 1},  {1, 1},  {1, 1},  {1, 1},  {1, 2},
-                             {1, 2},  {1, 4},  {2, 2},  {2, 2},  {1, 4},  {2, 4},  {1, 16},
-                             {1, 16}, {1, 16}, {1, 16}, {4, 4},  {4, 4},  {4, 4},  {4, 8},
-                             {4, 8},  {4, 8},  {4, 8},  {4, 8},  {2, 32}, {2, 32}, {2, 32},
-                             {2, 32}, {2, 32}, {2, 32}, {2, 32}, {2, 32}, {2, 32}};
-  return t[S];
+  if (S <= 5) return {1, 1, 8, 8};
+  if (S <= 8) return {2, 2, 4, 4};
+  if (S <= 16) return {4, 4, 2, 2};
+  return {8, 8, 1, 1};
 }
+
+template <int R, int S> struct SideShape {
+  static constexpr Pattern pt = pattern(R, S);
+  static constexpr int GR = pt.gr, GC = pt.gc, BR = pt.br, BC = pt.bc;
+  static constexpr int G = GR * GC, WB = BR * BC;
+  static constexpr int U = (S + GR - 1) / GR, V = (S + GC - 1) / GC;
+  static constexpr int JRL = S - (U - 1) * GR, JCL = S - (V - 1) * GC;  // last slot extents
+  static constexpr int NRM = (R + S - 1) / S;   // most windows per region row
+  static constexpr int RB = (NRM + BR - 1) / BR, CB = (NRM + BC - 1) / BC;
+  // furthest pixel row / column (region-relative) any lane reads
+  static constexpr int MAXROW = (S - 1) + S * (RB * BR - 1) + U * GR - 1;
+  static constexpr int MAXCOL = (S - 1) + S * (CB * BC - 1) + V * GC - 1;
+  // furthest element (from the round start) a lane reads in the ring
+  static constexpr int MAXELEM = WB * S * S + G;
+  static_assert(G * WB == 64, "a round uses the whole wave");
+  // element offset of slot (u, v) inside a window
+  static constexpr int slot(int u, int v) {
+    return u * GR * S + (u == U - 1 ? JRL : GR) * v * GC;
+  }
+};
+
+template <typename TX, typename TQ, int R, int SMAX> struct PhaseShape {
+  static constexpr int FR = R + SMAX - 1;
+  static constexpr int mrow() {
+    int m = FR;
+    for (int s = 1; s <= SMAX; ++s) {
+      const Pattern p = pattern(R, s);
+      const int U = (s + p.gr - 1) / p.gr, nrm = (R + s - 1) / s, rb = (nrm + p.br - 1) / p.br;
+      const int r = (s - 1) + s * (rb * p.br - 1) + U * p.gr;
+      if (r > m) m = r;
+    }
+    return m;
+  }
+  static constexpr int mcol() {
+    int m = FR;
+    for (int s = 1; s <= SMAX; ++s) {
+      const Pattern p = pattern(R, s);
+      const int V = (s + p.gc - 1) / p.gc, nrm = (R + s - 1) / s, cb = (nrm + p.bc - 1) / p.bc;
+      const int c = (s - 1) + s * (cb * p.bc - 1) + V * p.gc;
+      if (c > m) m = c;
+    }
+    return m;
+  }
+  static constexpr int XROWS = mrow();
+  static constexpr int P = (mcol() % 2 == 0) ? mcol() + 1 : mcol();  // odd pitch
+  // scratch written by lanes without a window: largest immediate + 1
+  static constexpr int dummy() {
+    int m = 0;
+    for (int s = 1; s <= SMAX; ++s) {
+      const Pattern p = pattern(R, s);
+      const int U = (s + p.gr - 1) / p.gr, V = (s + p.gc - 1) / p.gc;
+      const int d = (U - 1) * p.gr * P + (V - 1) * p.gc + 1;
+      if (d > m) m = d;
+    }
+    return m;
+  }
+  static constexpr int XDUMMY = XROWS * P;
+  static constexpr int XSIZE = XROWS * P + dummy();
+  // mirrored ring pages: enough for the largest round read
+  static constexpr int mirror() {
+    int m = 0;
+    for (int s = 1; s <= SMAX; ++s) {
+      const Pattern p = pattern(R, s);
+      const int e = p.br * p.bc * s * s + p.gr * p.gc;
+      if (e > m) m = e;
+    }
+    return (m * (int)sizeof(TQ) + kPage - 1) / kPage + 1;
+  }
+  static constexpr int MIRROR = mirror();
+  static constexpr int RING = (kSlots + MIRROR) * kPage;
+  static_assert(MIRROR + 2 <= kSlots, "ring too small for a round");
+};
 
 // ---------------------------------------------------------------- reductions
 // All-reduce (sum) over aligned groups of G lanes; every lane of a group gets
@@ -190,157 +289,162 @@ struct PhaseArgs {
   float guard;          // FP32 recheck band (relative)
   int32_t sides[kMaxSides];  // descending
   float r2f[kMaxSides];
+  float rf[kMaxSides];       // sqrt(r2), FP32
   double r2d[kMaxSides];
 };
 
-template <typename TX, typename TQ, int R, int SMAX> struct PhaseShape {
-  static constexpr int FR = R + SMAX - 1;
-  static constexpr int P = (FR % 2 == 0) ? FR + 1 : FR;  // odd pitch: fewer bank conflicts
-};
-
 struct Consumer {
-  unsigned char* ring;
-  int* ready;     // pages (relative to p_lo) present in the ring
-  int* consumed;  // first page (relative) still needed
-  int64_t p_lo;
-  int64_t qpos;   // next increment element of this region
-  int r0, c0;     // anchor origin of the region (= footprint origin)
+  const unsigned char* ring;
+  int* ready;      // pages (relative to the region's first page) present in the ring
+  int* consumed;   // first page (relative) still needed
+  __amdgpu_buffer_rsrc_t rsrc;  // the region's increments
+  uint32_t qb;     // next increment byte of the region (relative)
+  uint32_t pb0;    // byte offset of the region start inside its first page
+  uint32_t rb0;    // ring byte offset of the region start
+  int r0, c0;      // anchor origin of the region (= footprint origin)
   int lane;
+  int ready_seen;  // last value read from *ready
 };
 
-template <typename TX, typename TQ, int R, int SMAX, int S>
+template <typename TX, typename TQ, int R, int SMAX, int S, bool KAHAN>
 __device__ __forceinline__ void run_side(const PhaseArgs& a, Consumer& c, TX* xs, int k) {
-  constexpr Pattern pt = pattern(R, S);
-  constexpr int GR = pt.gr, GC = pt.gc, G = GR * GC, WR = 64 / G;
-  constexpr int U = (S + GR - 1) / GR, V = (S + GC - 1) / GC;
-  constexpr int P = PhaseShape<TX, TQ, R, SMAX>::P;
+  using SS = SideShape<R, S>;
+  using LS = PhaseShape<TX, TQ, R, SMAX>;
+  constexpr int GR = SS::GR, GC = SS::GC, G = SS::G, BR = SS::BR, BC = SS::BC;
+  constexpr int U = SS::U, V = SS::V, JRL = SS::JRL, JCL = SS::JCL;
+  constexpr int P = LS::P;
   constexpr int ES = (int)sizeof(TQ);
+  constexpr uint32_t RMASK = kSlots * kPage - 1;
   using QS = QStore<TQ, TX>;
 
-  const int wl = c.lane / G, jj = c.lane % G, jr = jj / GC, jc = jj % GC;
-  const int rhi = min(c.r0 + R, a.H - S + 1), chi = min(c.c0 + R, a.W - S + 1);
+  const int wl = c.lane / G, jj = c.lane % G;
+  const int bry = wl / BC, brx = wl % BC, jr = jj / GC, jc = jj % GC;
+  const bool rl = jr < JRL, cl = jc < JCL;     // lane holds a pixel in the last row / col slot
+  const int ef = jr * GC + jc, el = jr * JCL + jc;  // element of the lane inside a slot
+  const int lane_x0 = (S * bry + jr) * P + (S * brx + jc);
+  const int rhi = min(R, a.H - S + 1 - c.r0), chi = min(R, a.W - S + 1 - c.c0);
+  if (rhi <= 0 || chi <= 0) return;
   const TX r2 = (sizeof(TX) == 8) ? (TX)a.r2d[k] : (TX)a.r2f[k];
+  const float rfl = a.rf[k];
   const double r2d = a.r2d[k];
-  TQ* qg = (TQ*)a.q;
 
-  // Per-lane rank of its element inside a slot, for the (up to) four shapes
-  // of slot: full / partial row block x full / partial column block.
-  int rank[2][2];
-#pragma unroll
-  for (int ur = 0; ur < 2; ++ur)
-#pragma unroll
-    for (int vc = 0; vc < 2; ++vc) {
-      const int jrn = ur ? (S - (U - 1) * GR) : GR;
-      const int jcn = vc ? (S - (V - 1) * GC) : GC;
-      rank[ur][vc] = wl * jrn * jcn + jr * jcn + jc;
-    }
+  for (int ap = 0; ap < S; ++ap) {
+    const int nr = (rhi - ap + S - 1) / S;
+    if (ap >= rhi) break;
+    for (int bp = 0; bp < S; ++bp) {
+      if (bp >= chi) break;
+      const int nc = (chi - bp + S - 1) / S;
+      for (int rby = 0; rby < nr; rby += BR) {
+        const int nbr = min(BR, nr - rby);
+        for (int rbx = 0; rbx < nc; rbx += BC) {
+          const int nbc = min(BC, nc - rbx);
+          const int nwr = nbr * nbc;
+          const bool valid = bry < nbr && brx < nbc;
+          const int woff = (bry * nbc + brx) * (S * S);
+          const uint32_t rb = c.qb;
+          c.qb += (uint32_t)(nwr * S * S * ES);
+          // wait until every page holding this round's bytes is in the ring
+          const int need = (int)((c.pb0 + c.qb + kPage - 1) / kPage);
+          if (need > c.ready_seen) {
+            while ((c.ready_seen = lds_load(c.ready)) < need) __builtin_amdgcn_s_sleep(1);
+          }
+          __asm__ volatile("" ::: "memory");
+          const uint32_t roff = (c.rb0 + rb) & RMASK;
+          // ring addresses (full / last column slots) and masked store offsets
+          const unsigned char* qrf = c.ring + roff + (woff + ef) * ES;
+          const unsigned char* qrl = c.ring + roff + (woff + el) * ES;
+          const uint32_t sff = valid ? (uint32_t)((woff + ef) * ES) : kDropOffset;
+          const uint32_t sfl = valid && cl ? (uint32_t)((woff + el) * ES) : kDropOffset;
+          const uint32_t slf = valid && rl ? (uint32_t)((woff + ef) * ES) : kDropOffset;
+          const uint32_t sll = valid && rl && cl ? (uint32_t)((woff + el) * ES) : kDropOffset;
+          const int bx = lane_x0 + (ap + S * rby) * P + (bp + S * rbx);
+          const int bxr = valid ? bx : 0;
+          const int bxw = valid ? bx : LS::XDUMMY;
+          const int bxw_r = valid && rl ? bx : LS::XDUMMY;
+          const int bxw_c = valid && cl ? bx : LS::XDUMMY;
+          const int bxw_rc = valid && rl && cl ? bx : LS::XDUMMY;
 
-  for (int oa = 0; oa < S; ++oa) {
-    const int i0 = c.r0 + ((oa - c.r0 % S) % S + S) % S;
-    const int nr = i0 < rhi ? (rhi - i0 + S - 1) / S : 0;
-    if (nr == 0) continue;
-    for (int ob = 0; ob < S; ++ob) {
-      const int j0 = c.c0 + ((ob - c.c0 % S) % S + S) % S;
-      const int nc = j0 < chi ? (chi - j0 + S - 1) / S : 0;
-      const int nw = nr * nc;
-      for (int rb = 0; rb < nw; rb += WR) {
-        const int nwr = min(WR, nw - rb);
-        const bool valid = wl < nwr;
-        const int w = rb + wl;
-        const int wy = w / nc, wx = w - (w / nc) * nc;
-        const int xb = (i0 - c.r0 + wy * S + jr) * P + (j0 - c.c0 + wx * S + jc);
-        const int64_t chunk = c.qpos;
-        c.qpos += (int64_t)nwr * S * S;
-        // wait until every page holding [chunk, qpos) is in the ring
-        const int need = (int)((c.qpos * ES + kPage - 1) / kPage - c.p_lo);
-        while (lds_load(c.ready) < need) __builtin_amdgcn_s_sleep(1);
-        __asm__ volatile("" ::: "memory");
-        const uint32_t cb = (uint32_t)((uint64_t)chunk * ES);
-        TQ* qr = qg + chunk;
-
-        TX y[U][V];
-        TX acc = 0, comp = 0;
+          // 1) LDS reads: pixels at immediates off one base, increments off two
+          TX xv[U][V], qv[U][V];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+          for (int u = 0; u < U; ++u)
 #pragma unroll
-          for (int v = 0; v < V; ++v) {
-            const int jrn = (u == U - 1) ? (S - (U - 1) * GR) : GR;
-            const int jcn = (v == V - 1) ? (S - (V - 1) * GC) : GC;
-            const int cuv = u * GR * S + jrn * v * GC;
-            const bool in = valid && (jr < jrn) && (jc < jcn);
-            TX yv = 0;
-            if (in) {
-              const int rk = rank[u == U - 1 ? 1 : 0][v == V - 1 ? 1 : 0];
-              const uint32_t off = (cb + (uint32_t)((nwr * cuv + rk) * ES)) & (kRing - 1);
-              const TX qv = QS::get(c.ring + off);
-              yv = xs[xb + u * GR * P + v * GC] + qv;
+            for (int v = 0; v < V; ++v) {
+              qv[u][v] = QS::get((v == V - 1 ? qrl : qrf) + SS::slot(u, v) * ES);
+              xv[u][v] = xs[bxr + u * GR * P + v * GC];
             }
-            y[u][v] = yv;
-            if constexpr (sizeof(TX) == 4) {
-              if (a.kahan) {
+          // 2) y = x + I (pixels outside the window count as 0), sum of squares
+          TX y[U][V];
+          TX acc = 0, comp = 0;
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+              TX yv = xv[u][v] + qv[u][v];
+              const bool part_r = (u == U - 1) && (JRL < GR);
+              const bool part_c = (v == V - 1) && (JCL < GC);
+              if (part_r && part_c) yv = (rl && cl) ? yv : TX(0);
+              else if (part_r) yv = rl ? yv : TX(0);
+              else if (part_c) yv = cl ? yv : TX(0);
+              y[u][v] = yv;
+              if constexpr (sizeof(TX) == 4 && KAHAN) {
                 const TX t2 = __builtin_fmaf(yv, yv, -comp);
                 const TX s2 = acc + t2;
                 comp = (s2 - acc) - t2;
                 acc = s2;
-              } else {
+              } else if constexpr (sizeof(TX) == 4) {
                 acc = __builtin_fmaf(yv, yv, acc);
+              } else {
+                acc = __builtin_fma(yv, yv, acc);
               }
-            } else {
-              acc = __builtin_fma(yv, yv, acc);
             }
-          }
-        if constexpr (sizeof(TX) == 4) acc -= comp;
-        TX n = group_sum<G>(acc);
-        TX t = 1;
-        if constexpr (sizeof(TX) == 4) {
-          // FP64 recheck of windows whose sum lies within the guard band.
-          const bool near = a.guard > 0.f && fabsf(n - r2) <= a.guard * r2;
-          if (__builtin_amdgcn_read_exec() & __ballot(near)) {
-            double pd = 0.0;
+          if constexpr (sizeof(TX) == 4 && KAHAN) acc -= comp;
+          const TX n = group_sum<G>(acc);
+          TX t;
+          if constexpr (sizeof(TX) == 4) {
+            t = n > r2 ? rfl * __builtin_amdgcn_rsqf(n) : 1.0f;
+            // FP64 recheck of windows whose sum lies within the guard band.
+            const bool near = fabsf(n - r2) <= a.guard * r2;
+            if (__any(near)) {
+              double pd = 0.0;
 #pragma unroll
-            for (int u = 0; u < U; ++u)
+              for (int u = 0; u < U; ++u)
 #pragma unroll
-              for (int v = 0; v < V; ++v) pd = __builtin_fma((double)y[u][v], (double)y[u][v], pd);
-            const double nd = group_sum<G>(pd);
-            if (near) {
-              t = nd > r2d ? (float)__builtin_sqrt(r2d / nd) : 1.0f;
-            } else if (n > r2) {
-              t = __builtin_sqrtf(r2 / n);
+                for (int v = 0; v < V; ++v)
+                  pd = __builtin_fma((double)y[u][v], (double)y[u][v], pd);
+              const double nd = group_sum<G>(pd);
+              if (near) t = nd > r2d ? (float)__builtin_sqrt(r2d / nd) : 1.0f;
             }
-          } else if (n > r2) {
-            t = __builtin_sqrtf(r2 / n);
+          } else {
+            t = n > r2 ? __builtin_sqrt(r2 / n) : TX(1);
           }
-        } else {
-          if (n > r2) t = __builtin_sqrt(r2 / n);
-        }
+          // 3) x' = t y into the footprint, I' = y - x' to HBM
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+          for (int u = 0; u < U; ++u)
 #pragma unroll
-          for (int v = 0; v < V; ++v) {
-            const int jrn = (u == U - 1) ? (S - (U - 1) * GR) : GR;
-            const int jcn = (v == V - 1) ? (S - (V - 1) * GC) : GC;
-            const int cuv = u * GR * S + jrn * v * GC;
-            const bool in = valid && (jr < jrn) && (jc < jcn);
-            if (in) {
-              const int rk = rank[u == U - 1 ? 1 : 0][v == V - 1 ? 1 : 0];
+            for (int v = 0; v < V; ++v) {
+              const bool part_r = (u == U - 1) && (JRL < GR);
+              const bool part_c = (v == V - 1) && (JCL < GC);
+              const int base = (part_r && part_c) ? bxw_rc : part_r ? bxw_r : part_c ? bxw_c : bxw;
+              const uint32_t so = (u == U - 1) ? ((v == V - 1) ? sll : slf) : ((v == V - 1) ? sfl : sff);
               const TX xn = t * y[u][v];
-              xs[xb + u * GR * P + v * GC] = xn;
-              QS::put(qr + (nwr * cuv + rk), y[u][v] - xn);
+              xs[base + u * GR * P + v * GC] = xn;
+              QS::put(c.rsrc, so, rb + SS::slot(u, v) * ES, y[u][v] - xn);
             }
-          }
-        __asm__ volatile("" ::: "memory");
-        lds_store(c.consumed, (int)((c.qpos * ES) / kPage - c.p_lo));
+          __asm__ volatile("" ::: "memory");
+          lds_store(c.consumed, (int)((c.pb0 + c.qb) / kPage));
+        }
       }
     }
   }
 }
 
-template <typename TX, typename TQ, int R, int SMAX>
+template <typename TX, typename TQ, int R, int SMAX, bool KAHAN>
 __device__ __forceinline__ void dispatch_side(const PhaseArgs& a, Consumer& c, TX* xs, int k) {
   switch (a.sides[k]) {
 #define SMRE_SIDE_CASE(n) \
   case n:                 \
-    if constexpr (n <= SMAX) run_side<TX, TQ, R, SMAX, n>(a, c, xs, k); \
+    if constexpr (n <= SMAX) run_side<TX, TQ, R, SMAX, n, KAHAN>(a, c, xs, k); \
     break;
     SMRE_SIDE_CASE(1) SMRE_SIDE_CASE(2) SMRE_SIDE_CASE(3) SMRE_SIDE_CASE(4) SMRE_SIDE_CASE(5)
     SMRE_SIDE_CASE(6) SMRE_SIDE_CASE(7) SMRE_SIDE_CASE(8) SMRE_SIDE_CASE(9) SMRE_SIDE_CASE(10)
@@ -356,39 +460,53 @@ __device__ __forceinline__ void dispatch_side(const PhaseArgs& a, Consumer& c, T
 }
 
 // Producer wave: copy pages [p_lo, p_hi) of the increment stream into the
-// ring, kPrefetch loads in flight, never more than kSlots pages ahead of the
-// consumer.
+// ring (slot = page mod kSlots; slots below MIRROR also after the ring end),
+// kPrefetch loads in flight, never more than kSlots pages ahead of the
+// consumer.  Full batches of kPrefetch pages run branch-free so the loads stay
+// in flight across batches; the last partial batch drains.
+template <int MIRROR>
+__device__ __forceinline__ void put_page(u32x4* ring, int64_t page, int rel, int lane, u32x4 v,
+                                         int* ready, const int* consumed, int& cons_seen) {
+  if (rel >= cons_seen + kSlots) {
+    while (rel >= (cons_seen = lds_load(consumed)) + kSlots) __builtin_amdgcn_s_sleep(2);
+  }
+  __asm__ volatile("" ::: "memory");
+  const int slot = (int)(page & (kSlots - 1));
+  ring[slot * 64 + lane] = v;
+  if (slot < MIRROR) ring[(kSlots + slot) * 64 + lane] = v;
+  lds_store(ready, rel + 1);
+}
+
+template <int MIRROR>
 __device__ __forceinline__ void produce(const u32x4* src, int64_t p_lo, int64_t p_hi, u32x4* ring,
                                         int* ready, const int* consumed, int lane) {
   const int npg = (int)(p_hi - p_lo);
   if (npg <= 0) return;
+  int cons_seen = 0;
   u32x4 buf[kPrefetch];
 #pragma unroll
-  for (int k = 0; k < kPrefetch; ++k) {
-    const int64_t pg = p_lo + min(k, npg - 1);
-    buf[k] = __builtin_nontemporal_load(src + pg * 64 + lane);
-  }
-  for (int base = 0; base < npg; base += kPrefetch) {
+  for (int k = 0; k < kPrefetch; ++k)
+    buf[k] = __builtin_nontemporal_load(src + (p_lo + min(k, npg - 1)) * 64 + lane);
+  int base = 0;
+  for (; base + kPrefetch <= npg; base += kPrefetch) {
 #pragma unroll
     for (int k = 0; k < kPrefetch; ++k) {
-      const int pg = base + k;
-      if (pg < npg) {
-        while (pg >= lds_load(consumed) + kSlots) __builtin_amdgcn_s_sleep(1);
-        __asm__ volatile("" ::: "memory");
-        ring[(int)((p_lo + pg) % kSlots) * 64 + lane] = buf[k];
-        lds_store(ready, pg + 1);
-        const int64_t nx = p_lo + min(pg + kPrefetch, npg - 1);
-        buf[k] = __builtin_nontemporal_load(src + nx * 64 + lane);
-      }
+      const int rel = base + k;
+      put_page<MIRROR>(ring, p_lo + rel, rel, lane, buf[k], ready, consumed, cons_seen);
+      buf[k] = __builtin_nontemporal_load(src + (p_lo + min(rel + kPrefetch, npg - 1)) * 64 + lane);
     }
   }
+#pragma unroll
+  for (int k = 0; k < kPrefetch; ++k)
+    if (base + k < npg)
+      put_page<MIRROR>(ring, p_lo + base + k, base + k, lane, buf[k], ready, consumed, cons_seen);
 }
 
-template <typename TX, typename TQ, int R, int SMAX>
+template <typename TX, typename TQ, int R, int SMAX, bool KAHAN>
 __global__ __launch_bounds__(128) void region_phase(PhaseArgs a) {
   using SH = PhaseShape<TX, TQ, R, SMAX>;
-  __shared__ __attribute__((aligned(16))) unsigned char ring[kRing];
-  __shared__ TX xs[SH::FR * SH::P];
+  __shared__ __attribute__((aligned(16))) unsigned char ring[SH::RING];
+  __shared__ TX xs[SH::XSIZE];
   __shared__ int ctr[2];
   if (*a.done) return;
 
@@ -396,8 +514,9 @@ __global__ __launch_bounds__(128) void region_phase(PhaseArgs a) {
   const int ry = a.cy + 2 * (b / a.ncx), rx = a.cx + 2 * (b % a.ncx);
   const int region = ry * a.nrx + rx;
   const int64_t e_lo = a.roff[region], e_hi = a.roff[region + 1];
-  const int64_t p_lo = (e_lo * (int64_t)sizeof(TQ)) / kPage;
-  const int64_t p_hi = (e_hi * (int64_t)sizeof(TQ) + kPage - 1) / kPage;
+  const int64_t byte_lo = e_lo * (int64_t)sizeof(TQ), byte_hi = e_hi * (int64_t)sizeof(TQ);
+  const int64_t p_lo = byte_lo / kPage;
+  const int64_t p_hi = (byte_hi + kPage - 1) / kPage;
   const int lane = threadIdx.x & 63;
   if (threadIdx.x == 0) {
     ctr[0] = 0;
@@ -406,7 +525,7 @@ __global__ __launch_bounds__(128) void region_phase(PhaseArgs a) {
   __syncthreads();
 
   if (threadIdx.x >= 64) {
-    produce((const u32x4*)a.q, p_lo, p_hi, (u32x4*)ring, &ctr[0], &ctr[1], lane);
+    produce<SH::MIRROR>((const u32x4*)a.q, p_lo, p_hi, (u32x4*)ring, &ctr[0], &ctr[1], lane);
     return;
   }
 
@@ -419,8 +538,20 @@ __global__ __launch_bounds__(128) void region_phase(PhaseArgs a) {
   }
   __asm__ volatile("" ::: "memory");
 
-  Consumer c{ring, &ctr[0], &ctr[1], p_lo, e_lo, r0, c0, lane};
-  for (int k = 0; k < a.nsides; ++k) dispatch_side<TX, TQ, R, SMAX>(a, c, xs, k);
+  Consumer c;
+  c.ring = ring;
+  c.ready = &ctr[0];
+  c.consumed = &ctr[1];
+  c.rsrc = __builtin_amdgcn_make_buffer_rsrc((unsigned char*)a.q + byte_lo, (short)0,
+                                            (int)(byte_hi - byte_lo), kRsrcWord3);
+  c.qb = 0;
+  c.pb0 = (uint32_t)(byte_lo - p_lo * kPage);
+  c.rb0 = (uint32_t)(byte_lo & (kSlots * kPage - 1));
+  c.r0 = r0;
+  c.c0 = c0;
+  c.lane = lane;
+  c.ready_seen = 0;
+  for (int k = 0; k < a.nsides; ++k) dispatch_side<TX, TQ, R, SMAX, KAHAN>(a, c, xs, k);
 
   __asm__ volatile("" ::: "memory");
   for (int idx = lane; idx < fh * fw; idx += 64) {
@@ -464,30 +595,25 @@ __device__ __forceinline__ double block_max(double v) {
   return v;
 }
 
+// Image-wide passes: blocks stride over rows, threads over columns.
 template <typename TX>
 __global__ __launch_bounds__(256) void snapshot_kernel(const TX* x, int64_t ld, int H, int W,
                                                        TX* prev, Ctrl* ctrl) {
   if (ctrl->done) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->delta_key = dkey(0.0);
-  const int64_t n = (int64_t)H * W;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = i / W, col = i - r * W;
-    prev[i] = x[r * ld + col];
-  }
+  for (int r = blockIdx.x; r < H; r += gridDim.x)
+    for (int col = threadIdx.x; col < W; col += blockDim.x)
+      prev[(int64_t)r * W + col] = x[(int64_t)r * ld + col];
 }
 
 template <typename TX>
 __global__ __launch_bounds__(256) void delta_kernel(const TX* x, int64_t ld, int H, int W,
                                                     const TX* prev, Ctrl* ctrl) {
   if (ctrl->done) return;
-  const int64_t n = (int64_t)H * W;
   double m = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = i / W, col = i - r * W;
-    m = fmax(m, fabs((double)x[r * ld + col] - (double)prev[i]));
-  }
+  for (int r = blockIdx.x; r < H; r += gridDim.x)
+    for (int col = threadIdx.x; col < W; col += blockDim.x)
+      m = fmax(m, fabs((double)x[(int64_t)r * ld + col] - (double)prev[(int64_t)r * W + col]));
   m = block_max<TX>(m);
   if (threadIdx.x == 0) atomicMax(&ctrl->delta_key, dkey(m));
 }
@@ -505,14 +631,12 @@ __global__ void decide_kernel(Ctrl* ctrl, double tol, int sweep) {
 template <typename TX>
 __global__ __launch_bounds__(256) void nonfinite_kernel(const TX* x, int64_t ld, int H, int W,
                                                         Ctrl* ctrl) {
-  const int64_t n = (int64_t)H * W;
   int bad = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = i / W, col = i - r * W;
-    const double v = (double)x[r * ld + col];
-    bad |= !(v - v == 0.0);
-  }
+  for (int r = blockIdx.x; r < H; r += gridDim.x)
+    for (int col = threadIdx.x; col < W; col += blockDim.x) {
+      const double v = (double)x[(int64_t)r * ld + col];
+      bad |= !(v - v == 0.0);
+    }
   if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&ctrl->nonfinite, 1);
 }
 

@@ -205,30 +205,34 @@ int ensure_ctrl(smre_ctx* c) {
 }
 
 int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(8192, (n + 255) / 256)); }
+int grid_rows(int64_t H) { return (int)std::max<int64_t>(1, std::min<int64_t>(4096, H)); }
 
-template <typename TX, typename TQ, int R>
+template <typename TX, typename TQ, int R, bool KAHAN>
 void launch_phase(const PhaseArgs& a, int blocks, hipStream_t s) {
   constexpr int SMAX = R + 1;
-  hipLaunchKernelGGL((region_phase<TX, TQ, R, SMAX>), dim3(blocks), dim3(128), 0, s, a);
+  hipLaunchKernelGGL((region_phase<TX, TQ, R, SMAX, KAHAN>), dim3(blocks), dim3(128), 0, s, a);
 }
 
-template <typename TX, typename TQ>
+template <typename TX, typename TQ, bool KAHAN>
 int launch_phase_r(int R, const PhaseArgs& a, int blocks, hipStream_t s) {
   switch (R) {
-    case 8: launch_phase<TX, TQ, 8>(a, blocks, s); break;
-    case 16: launch_phase<TX, TQ, 16>(a, blocks, s); break;
-    case 32: launch_phase<TX, TQ, 32>(a, blocks, s); break;
+    case 8: launch_phase<TX, TQ, 8, KAHAN>(a, blocks, s); break;
+    case 16: launch_phase<TX, TQ, 16, KAHAN>(a, blocks, s); break;
+    case 32: launch_phase<TX, TQ, 32, KAHAN>(a, blocks, s); break;
     default: return SMRE_EINVAL;
   }
   HIP_OK(hipGetLastError());
   return SMRE_OK;
 }
 
-int launch_phase_any(smre_dtype dt, int inc, int R, const PhaseArgs& a, int blocks,
+int launch_phase_any(smre_dtype dt, int inc, int kahan, int R, const PhaseArgs& a, int blocks,
                      hipStream_t s) {
-  if (dt == SMRE_F64) return launch_phase_r<double, double>(R, a, blocks, s);
-  if (inc == SMRE_INC_BF16) return launch_phase_r<float, bf16_t>(R, a, blocks, s);
-  return launch_phase_r<float, float>(R, a, blocks, s);
+  if (dt == SMRE_F64) return launch_phase_r<double, double, false>(R, a, blocks, s);
+  if (inc == SMRE_INC_BF16)
+    return kahan ? launch_phase_r<float, bf16_t, true>(R, a, blocks, s)
+                 : launch_phase_r<float, bf16_t, false>(R, a, blocks, s);
+  return kahan ? launch_phase_r<float, float, true>(R, a, blocks, s)
+               : launch_phase_r<float, float, false>(R, a, blocks, s);
 }
 
 template <typename TX>
@@ -249,7 +253,7 @@ int run_violation(smre_ctx* c, const void* x, int64_t H, int64_t W, int64_t ld, 
 template <typename TX>
 int check_nonfinite(smre_ctx* c, const void* x, int64_t H, int64_t W, int64_t ld, hipStream_t s,
                     bool* bad) {
-  hipLaunchKernelGGL((nonfinite_kernel<TX>), dim3(grid_for(H * W)), dim3(256), 0, s,
+  hipLaunchKernelGGL((nonfinite_kernel<TX>), dim3(grid_rows(H)), dim3(256), 0, s,
                      (const TX*)x, ld, (int)H, (int)W, c->ctrl);
   HIP_OK(hipGetLastError());
   HIP_OK(hipMemcpyAsync(c->ctrl_host, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
@@ -293,6 +297,7 @@ int project_impl(smre_ctx* c, smre_dtype dt, void* x, int64_t H, int64_t W, int6
   for (int k = 0; k < pl.nsides; ++k) {
     a.sides[k] = pl.sides[k];
     a.r2f[k] = (float)pl.r2[k];
+    a.rf[k] = (float)std::sqrt(pl.r2[k]);
     a.r2d[k] = pl.r2[k];
   }
   TX* prev = (TX*)(ws + pl.off_prev);
@@ -305,7 +310,7 @@ int project_impl(smre_ctx* c, smre_dtype dt, void* x, int64_t H, int64_t W, int6
   for (sweep = 1; sweep <= p->max_sweeps && !host_done; ++sweep) {
     const bool check = checking && (sweep % p->check_every == 0 || sweep == p->max_sweeps);
     if (check)
-      hipLaunchKernelGGL((snapshot_kernel<TX>), dim3(grid_for(H * W)), dim3(256), 0, s,
+      hipLaunchKernelGGL((snapshot_kernel<TX>), dim3(grid_rows(H)), dim3(256), 0, s,
                          (const TX*)x, ld, (int)H, (int)W, prev, c->ctrl);
     for (int color = 0; color < 4; ++color) {
       a.cy = color >> 1;
@@ -316,13 +321,13 @@ int project_impl(smre_ctx* c, smre_dtype dt, void* x, int64_t H, int64_t W, int6
       int slot;
       rc = timing_begin(c, tacc, s, &slot);
       if (rc) return rc;
-      rc = launch_phase_any(dt, p->inc, pl.R, a, ny * nx, s);
+      rc = launch_phase_any(dt, p->inc, p->kahan, pl.R, a, ny * nx, s);
       if (rc) return rc;
       rc = timing_end(c, tacc, s, slot);
       if (rc) return rc;
     }
     if (check) {
-      hipLaunchKernelGGL((delta_kernel<TX>), dim3(grid_for(H * W)), dim3(256), 0, s,
+      hipLaunchKernelGGL((delta_kernel<TX>), dim3(grid_rows(H)), dim3(256), 0, s,
                          (const TX*)x, ld, (int)H, (int)W, (const TX*)prev, c->ctrl);
       hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(1), 0, s, c->ctrl, p->tol, sweep);
       HIP_OK(hipGetLastError());
