@@ -77,9 +77,10 @@ typedef struct smre_ctx smre_ctx;
  * sets (Sec. 2.3), so the library uses an order that needs no ordering
  * between overlapping sets inside a kernel: the anchor (top-left) plane is cut
  * into R x R regions coloured 2 (p mod 2) + (q mod 2); colour by colour, each
- * region visits its windows side by side (descending), offset (a, b) by offset
- * in raster order, where offset (a, b) selects the disjoint tiling of anchors
- * congruent to (a, b) mod s.  Regions of one colour touch disjoint pixels.
+ * region (p, q) visits its windows side by side (descending), then offset
+ * (a', b') in raster order, where offset (a', b') selects the windows anchored
+ * at (p R + a' + s i, q R + b' + s j) -- disjoint, so projected together.
+ * Regions of one colour touch disjoint pixels.
  */
 typedef struct {
   int32_t n_sides;
@@ -151,6 +152,50 @@ int smre_dykstra_incomplete(smre_ctx* ctx, smre_dtype dtype, void* x, int64_t H,
                             int64_t ld, int32_t K, const double* radius2, double tol,
                             int32_t tolmode, int32_t max_inner, int32_t num_phases, void* stream,
                             smre_report* report);
+
+/* ---- Batches: images of different sizes in one persistent launch per colour ----
+ * Each image carries its own sides, bounds, tolerance and sweep cap; the
+ * batch shares dtype, increment storage, Kahan flag, check cadence and the
+ * region side R (all images need R >= their max side - 1).  One sweep is four
+ * persistent launches (one per region colour) walking device work lists of
+ * (image, region) items, then a per-image FP64 convergence check; images that
+ * converge (or reach their cap) are retired and their items skipped.  Sweeps
+ * are captured once in a HIP graph and replayed.  Every image gets exactly
+ * the arithmetic it gets alone with the same R, so batched and single results
+ * are bitwise equal. */
+typedef struct {
+  void* x;               /* device image (dtype of the call), row stride ld, in place */
+  int64_t H, W, ld;
+  int32_t n_sides;
+  const int32_t* sides;  /* host */
+  const double* radius2; /* host */
+  double tol;            /* <= 0: run exactly max_sweeps sweeps */
+  int32_t max_sweeps;
+  int32_t reserved;
+} smre_batch_image;
+
+typedef struct {
+  int32_t region;        /* 0 = autotune (cached in the context), else 8, 16 or 32 */
+  int32_t inc;           /* smre_inc */
+  int32_t kahan;
+  int32_t check_every;   /* >= 1 */
+  double guard_rel;
+  int32_t use_graph;     /* replay HIP-graph-captured sweeps (1) or launch directly (0) */
+  int32_t grid;          /* persistent workgroups per launch, 0 = from occupancy */
+} smre_batch_params;
+
+/* Device workspace bytes for a batch (covers every region side the tuner tries). */
+int smre_batch_workspace_size(smre_dtype dtype, int32_t n, const smre_batch_image* imgs,
+                              const smre_batch_params* bp, size_t* bytes);
+
+/* Full Dykstra on n images at once; reports[n] (host) receives one report
+ * per image (may be NULL).  workspace as in smre_dykstra_project.  Returns
+ * SMRE_OK if every image with tol > 0 converged, SMRE_NOT_CONVERGED if some
+ * hit their cap (results written), or an error. */
+int smre_dykstra_project_batch(smre_ctx* ctx, smre_dtype dtype, int32_t n,
+                               const smre_batch_image* imgs, const smre_batch_params* bp,
+                               void* workspace, size_t ws_bytes, void* stream,
+                               smre_report* reports);
 
 /* FP64 feasibility of x (device): *out = max_S sum_S x^2 / r2_S - 1 over all
  * windows of the given sides (<= 0 means every constraint holds). */

@@ -48,6 +48,20 @@ class Report(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class BatchImage(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("H", ctypes.c_int64), ("W", ctypes.c_int64),
+                ("ld", ctypes.c_int64), ("n_sides", ctypes.c_int32),
+                ("sides", ctypes.POINTER(ctypes.c_int32)),
+                ("radius2", ctypes.POINTER(ctypes.c_double)), ("tol", ctypes.c_double),
+                ("max_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class BatchParams(ctypes.Structure):
+    _fields_ = [("region", ctypes.c_int32), ("inc", ctypes.c_int32), ("kahan", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("guard_rel", ctypes.c_double),
+                ("use_graph", ctypes.c_int32), ("grid", ctypes.c_int32)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
@@ -71,6 +85,12 @@ def _load():
     L.smre_dykstra_incomplete.argtypes = [vp, ctypes.c_int, vp, i64, i64, i64, i32, dp, dbl,
                                           i32, i32, i32, vp, ctypes.POINTER(Report)]
     L.smre_max_violation.argtypes = [vp, ctypes.c_int, vp, i64, i64, i64, i32, ip, dp, vp, dp]
+    L.smre_batch_workspace_size.argtypes = [ctypes.c_int, i32, ctypes.POINTER(BatchImage),
+                                            ctypes.POINTER(BatchParams),
+                                            ctypes.POINTER(ctypes.c_size_t)]
+    L.smre_dykstra_project_batch.argtypes = [vp, ctypes.c_int, i32, ctypes.POINTER(BatchImage),
+                                             ctypes.POINTER(BatchParams), vp, ctypes.c_size_t,
+                                             vp, ctypes.POINTER(Report)]
     return L
 
 
@@ -78,7 +98,8 @@ _lib = _load()
 
 EXPORTS = ["smre_status_string", "smre_ctx_create", "smre_ctx_destroy", "smre_ctx_set_timing",
            "smre_chi2_bounds", "smre_paper_bounds", "smre_workspace_size",
-           "smre_dykstra_project", "smre_dykstra_incomplete", "smre_max_violation"]
+           "smre_dykstra_project", "smre_dykstra_incomplete", "smre_max_violation",
+           "smre_batch_workspace_size", "smre_dykstra_project_batch"]
 
 
 def lib():
@@ -231,6 +252,41 @@ class Context:
                                           ctypes.byref(rep))
         _check(rc, "smre_dykstra_incomplete")
         return rep.as_dict()
+
+    def project_batch(self, xs, sides, radius2, tol=1e-5, max_sweeps=5000, region=0,
+                      inc=INC_SAME, kahan=True, check_every=1, guard_rel=1e-5, use_graph=True,
+                      grid=0, stream=None):
+        """Full Dykstra on a list of 2-D CUDA tensors (same dtype), in place.
+
+        sides / radius2 / tol / max_sweeps may be per-image lists or shared.
+        Returns (status, list of report dicts)."""
+        n = len(xs)
+        if n == 0:
+            raise ValueError("empty batch")
+        dt = _dtype_code(xs[0])
+        per = lambda v: v if (isinstance(v, (list, tuple)) and len(v) == n and
+                              hasattr(v[0], "__len__")) else [v] * n
+        sides_l, r2_l = per(sides), per(radius2)
+        tol_l = tol if isinstance(tol, (list, tuple)) else [tol] * n
+        ms_l = max_sweeps if isinstance(max_sweeps, (list, tuple)) else [max_sweeps] * n
+        imgs = (BatchImage * n)()
+        keep = []
+        for i, x in enumerate(xs):
+            if _dtype_code(x) != dt:
+                raise TypeError("all images need one dtype")
+            H, W, ld = _image(x)
+            sv, sp = _ivec(sides_l[i])
+            rv, rp = _dvec(r2_l[i])
+            keep += [sv, rv]
+            imgs[i] = BatchImage(x.data_ptr(), H, W, ld, len(sv), sp, rp, float(tol_l[i]),
+                                 int(ms_l[i]), 0)
+        bp = BatchParams(int(region), int(inc), 1 if kahan else 0, int(check_every),
+                         float(guard_rel), 1 if use_graph else 0, int(grid))
+        reps = (Report * n)()
+        rc = _lib.smre_dykstra_project_batch(self._h, dt, n, imgs, ctypes.byref(bp), None, 0,
+                                             _stream(stream), reps)
+        _check(rc, "smre_dykstra_project_batch", allow=(OK, NOT_CONVERGED))
+        return rc, [r.as_dict() for r in reps]
 
     def max_violation(self, x, sides, radius2, stream=None):
         H, W, ld = _image(x)

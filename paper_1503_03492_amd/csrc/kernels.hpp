@@ -273,24 +273,41 @@ __device__ __forceinline__ void lds_store(int* p, int v) {
 }
 
 // ---------------------------------------------------------------- phase kernel
-struct PhaseArgs {
+// Everything a region job needs about its image.  Passed by value for a
+// single image; an array in device memory for a batch.
+struct ImageDesc {
   void* x;              // image (TX), row stride ld
-  const int64_t* roff;  // increment offset (elements) of each region, raster, +1 sentinel
-  void* q;              // increment stream (TQ)
-  const int* done;      // device flag: converged, skip remaining work
+  const int64_t* roff;  // increment offset (elements, from q_byte) of each region, +1 sentinel
   int64_t ld;
+  int64_t q_byte;       // first byte of this image's increments in the stream
   int32_t H, W;
-  int32_t nrx;          // regions per row
-  int32_t cy, cx;       // colour of this launch
-  int32_t ncx;          // regions of this colour per row
+  int32_t nrx, nry;     // region grid
   int32_t fr;           // footprint side R + smax - 1
   int32_t nsides;
-  int32_t kahan;
   float guard;          // FP32 recheck band (relative)
+  int32_t pad;
   int32_t sides[kMaxSides];  // descending
   float r2f[kMaxSides];
   float rf[kMaxSides];       // sqrt(r2), FP32
   double r2d[kMaxSides];
+};
+
+// Per-image state of a batched solve, in device memory.
+struct BatchCtl {
+  int done;                      // retired (converged or capped): its work items are skipped
+  int done_sweep;                // sweep at which it was retired
+  int converged;                 // 1 if the tolerance was met
+  int max_sweeps;
+  unsigned long long delta_key;  // running max |x - prev| of the checked sweep
+  double last_delta;
+  double tol;
+  int64_t prev_off;              // element offset of the image's snapshot
+};
+
+// One region of one image (a batch's work list holds these per colour).
+struct WorkItem {
+  int32_t img;
+  int32_t region;
 };
 
 struct Consumer {
@@ -307,7 +324,7 @@ struct Consumer {
 };
 
 template <typename TX, typename TQ, int R, int SMAX, int S, bool KAHAN>
-__device__ __forceinline__ void run_side(const PhaseArgs& a, Consumer& c, TX* xs, int k) {
+__device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs, int k) {
   using SS = SideShape<R, S>;
   using LS = PhaseShape<TX, TQ, R, SMAX>;
   constexpr int GR = SS::GR, GC = SS::GC, G = SS::G, BR = SS::BR, BC = SS::BC;
@@ -440,7 +457,7 @@ __device__ __forceinline__ void run_side(const PhaseArgs& a, Consumer& c, TX* xs
 }
 
 template <typename TX, typename TQ, int R, int SMAX, bool KAHAN>
-__device__ __forceinline__ void dispatch_side(const PhaseArgs& a, Consumer& c, TX* xs, int k) {
+__device__ __forceinline__ void dispatch_side(const ImageDesc& a, Consumer& c, TX* xs, int k) {
   switch (a.sides[k]) {
 #define SMRE_SIDE_CASE(n) \
   case n:                 \
@@ -502,36 +519,35 @@ __device__ __forceinline__ void produce(const u32x4* src, int64_t p_lo, int64_t 
       put_page<MIRROR>(ring, p_lo + base + k, base + k, lane, buf[k], ready, consumed, cons_seen);
 }
 
-template <typename TX, typename TQ, int R, int SMAX, bool KAHAN>
-__global__ __launch_bounds__(128) void region_phase(PhaseArgs a) {
+template <typename TX, typename TQ, int R, int SMAX> struct PhaseLds {
   using SH = PhaseShape<TX, TQ, R, SMAX>;
-  __shared__ __attribute__((aligned(16))) unsigned char ring[SH::RING];
-  __shared__ TX xs[SH::XSIZE];
-  __shared__ int ctr[2];
-  if (*a.done) return;
+  unsigned char ring[SH::RING];
+  TX xs[SH::XSIZE];
+  int ctr[2];
+};
 
-  const int b = blockIdx.x;
-  const int ry = a.cy + 2 * (b / a.ncx), rx = a.cx + 2 * (b % a.ncx);
-  const int region = ry * a.nrx + rx;
-  const int64_t e_lo = a.roff[region], e_hi = a.roff[region + 1];
-  const int64_t byte_lo = e_lo * (int64_t)sizeof(TQ), byte_hi = e_hi * (int64_t)sizeof(TQ);
+// One region of one image: both waves of the workgroup enter; the caller
+// synchronises the workgroup before and after.
+template <typename TX, typename TQ, int R, int SMAX, bool KAHAN>
+__device__ __forceinline__ void region_job(const ImageDesc& a, int region, unsigned char* q,
+                                           PhaseLds<TX, TQ, R, SMAX>& L) {
+  using SH = PhaseShape<TX, TQ, R, SMAX>;
+  const int ry = region / a.nrx, rx = region - (region / a.nrx) * a.nrx;
+  const int64_t byte_lo = a.q_byte + a.roff[region] * (int64_t)sizeof(TQ);
+  const int64_t byte_hi = a.q_byte + a.roff[region + 1] * (int64_t)sizeof(TQ);
   const int64_t p_lo = byte_lo / kPage;
   const int64_t p_hi = (byte_hi + kPage - 1) / kPage;
   const int lane = threadIdx.x & 63;
-  if (threadIdx.x == 0) {
-    ctr[0] = 0;
-    ctr[1] = 0;
-  }
-  __syncthreads();
 
   if (threadIdx.x >= 64) {
-    produce<SH::MIRROR>((const u32x4*)a.q, p_lo, p_hi, (u32x4*)ring, &ctr[0], &ctr[1], lane);
+    produce<SH::MIRROR>((const u32x4*)q, p_lo, p_hi, (u32x4*)L.ring, &L.ctr[0], &L.ctr[1], lane);
     return;
   }
 
   const int r0 = ry * R, c0 = rx * R;
   const int fh = min(a.fr, a.H - r0), fw = min(a.fr, a.W - c0);
   TX* xg = (TX*)a.x;
+  TX* xs = L.xs;
   for (int idx = lane; idx < fh * fw; idx += 64) {
     const int i = idx / fw, j = idx - (idx / fw) * fw;
     xs[i * SH::P + j] = xg[(int64_t)(r0 + i) * a.ld + c0 + j];
@@ -539,11 +555,11 @@ __global__ __launch_bounds__(128) void region_phase(PhaseArgs a) {
   __asm__ volatile("" ::: "memory");
 
   Consumer c;
-  c.ring = ring;
-  c.ready = &ctr[0];
-  c.consumed = &ctr[1];
-  c.rsrc = __builtin_amdgcn_make_buffer_rsrc((unsigned char*)a.q + byte_lo, (short)0,
-                                            (int)(byte_hi - byte_lo), kRsrcWord3);
+  c.ring = L.ring;
+  c.ready = &L.ctr[0];
+  c.consumed = &L.ctr[1];
+  c.rsrc = __builtin_amdgcn_make_buffer_rsrc(q + byte_lo, (short)0, (int)(byte_hi - byte_lo),
+                                            kRsrcWord3);
   c.qb = 0;
   c.pb0 = (uint32_t)(byte_lo - p_lo * kPage);
   c.rb0 = (uint32_t)(byte_lo & (kSlots * kPage - 1));
@@ -557,6 +573,45 @@ __global__ __launch_bounds__(128) void region_phase(PhaseArgs a) {
   for (int idx = lane; idx < fh * fw; idx += 64) {
     const int i = idx / fw, j = idx - (idx / fw) * fw;
     xg[(int64_t)(r0 + i) * a.ld + c0 + j] = xs[i * SH::P + j];
+  }
+}
+
+// One image, one colour: block b takes the b-th region of colour (cy, cx).
+template <typename TX, typename TQ, int R, int SMAX, bool KAHAN>
+__global__ __launch_bounds__(128) void region_phase(ImageDesc a, int cy, int cx, int ncx,
+                                                    const int* done, unsigned char* q) {
+  __shared__ PhaseLds<TX, TQ, R, SMAX> L;
+  if (*done) return;
+  const int b = blockIdx.x;
+  const int region = (cy + 2 * (b / ncx)) * a.nrx + cx + 2 * (b % ncx);
+  if (threadIdx.x == 0) {
+    L.ctr[0] = 0;
+    L.ctr[1] = 0;
+  }
+  __syncthreads();
+  region_job<TX, TQ, R, SMAX, KAHAN>(a, region, q, L);
+}
+
+// A batch of images, one colour: a persistent grid walks the colour's work
+// list; items of converged images are skipped.
+template <typename TX, typename TQ, int R, int SMAX, bool KAHAN>
+__global__ __launch_bounds__(128) void region_phase_batch(const ImageDesc* __restrict__ imgs,
+                                                          const BatchCtl* __restrict__ ctl,
+                                                          const WorkItem* __restrict__ items,
+                                                          const int* __restrict__ nitems,
+                                                          unsigned char* q) {
+  __shared__ PhaseLds<TX, TQ, R, SMAX> L;
+  const int n = *nitems;
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const WorkItem w = items[it];
+    if (ctl[w.img].done) continue;
+    if (threadIdx.x == 0) {
+      L.ctr[0] = 0;
+      L.ctr[1] = 0;
+    }
+    __syncthreads();
+    region_job<TX, TQ, R, SMAX, KAHAN>(imgs[w.img], w.region, q, L);
+    __syncthreads();
   }
 }
 
@@ -677,6 +732,72 @@ __global__ void ctrl_reset_kernel(Ctrl* c) {
   c->delta_key = dkey(0.0);
   c->last_delta = -1.0;
   c->viol_key = dkey(-1.0);
+}
+
+// ---------------------------------------------------------------- batch control
+template <typename TX>
+__global__ __launch_bounds__(256) void snapshot_batch(const ImageDesc* __restrict__ imgs,
+                                                      BatchCtl* ctl, TX* prev) {
+  const int im = blockIdx.y;
+  if (ctl[im].done) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl[im].delta_key = dkey(0.0);
+  const ImageDesc& a = imgs[im];
+  const TX* x = (const TX*)a.x;
+  TX* pv = prev + ctl[im].prev_off;
+  for (int r = blockIdx.x; r < a.H; r += gridDim.x)
+    for (int col = threadIdx.x; col < a.W; col += blockDim.x)
+      pv[(int64_t)r * a.W + col] = x[(int64_t)r * a.ld + col];
+}
+
+template <typename TX>
+__global__ __launch_bounds__(256) void delta_batch(const ImageDesc* __restrict__ imgs,
+                                                   BatchCtl* ctl, const TX* prev) {
+  const int im = blockIdx.y;
+  if (ctl[im].done) return;
+  const ImageDesc& a = imgs[im];
+  const TX* x = (const TX*)a.x;
+  const TX* pv = prev + ctl[im].prev_off;
+  double m = 0.0;
+  for (int r = blockIdx.x; r < a.H; r += gridDim.x)
+    for (int col = threadIdx.x; col < a.W; col += blockDim.x)
+      m = fmax(m, fabs((double)x[(int64_t)r * a.ld + col] - (double)pv[(int64_t)r * a.W + col]));
+  m = block_max<TX>(m);
+  if (threadIdx.x == 0) atomicMax(&ctl[im].delta_key, dkey(m));
+}
+
+// One block: close the sweep for every image (check and/or sweep cap) and
+// count the images still running.  counters[0] = sweeps done, [1] = active.
+__global__ __launch_bounds__(256) void decide_batch(BatchCtl* ctl, int n, int check,
+                                                    int* counters) {
+  __shared__ int active;
+  const int sweep = counters[0] + 1;
+  if (threadIdx.x == 0) active = 0;
+  __syncthreads();
+  for (int im = threadIdx.x; im < n; im += blockDim.x) {
+    BatchCtl& c = ctl[im];
+    if (c.done) continue;
+    bool stop = false;
+    if (check) {
+      const double d = dkey_inv(c.delta_key);
+      c.last_delta = d;
+      if (d < c.tol) {
+        c.converged = 1;
+        stop = true;
+      }
+    }
+    if (sweep >= c.max_sweeps) stop = true;
+    if (stop) {
+      c.done = 1;
+      c.done_sweep = sweep;
+    } else {
+      atomicAdd(&active, 1);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    counters[0] = sweep;
+    counters[1] = active;
+  }
 }
 
 }  // namespace smre

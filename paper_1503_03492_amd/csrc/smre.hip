@@ -17,6 +17,8 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <map>
+#include <string>
 #include <vector>
 
 #include "icd.hpp"
@@ -53,6 +55,10 @@ struct smre_ctx {
   int ev_used = 0;
   hipEvent_t t0 = nullptr, t1 = nullptr;
   std::vector<hipEvent_t> lag_ev;
+  int* counters_host = nullptr;      // pinned ring of batch counters
+  hipStream_t capture = nullptr;     // private stream for graph capture
+  std::map<std::string, int> tuned;  // autotuned region side per batch key
+  int cus = 0;
 };
 
 namespace {
@@ -200,6 +206,11 @@ int ensure_ctrl(smre_ctx* c) {
     for (int k = 0; k < 2 * kTimingPairs; ++k) HIP_OK(hipEventCreate(&c->ev[k]));
     HIP_OK(hipEventCreate(&c->t0));
     HIP_OK(hipEventCreate(&c->t1));
+    HIP_OK(hipHostMalloc(&c->counters_host, sizeof(int) * 2 * (kLag + 2), hipHostMallocDefault));
+    HIP_OK(hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
+    hipDeviceProp_t prop;
+    HIP_OK(hipGetDeviceProperties(&prop, c->device));
+    c->cus = prop.multiProcessorCount;
   }
   return SMRE_OK;
 }
@@ -207,32 +218,40 @@ int ensure_ctrl(smre_ctx* c) {
 int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(8192, (n + 255) / 256)); }
 int grid_rows(int64_t H) { return (int)std::max<int64_t>(1, std::min<int64_t>(4096, H)); }
 
+// One colour of one image: grid = regions of that colour.
+struct PhaseLaunch {
+  int cy, cx, ncx, blocks;
+  const int* done;
+  unsigned char* q;
+};
+
 template <typename TX, typename TQ, int R, bool KAHAN>
-void launch_phase(const PhaseArgs& a, int blocks, hipStream_t s) {
+void launch_phase(const ImageDesc& a, const PhaseLaunch& l, hipStream_t s) {
   constexpr int SMAX = R + 1;
-  hipLaunchKernelGGL((region_phase<TX, TQ, R, SMAX, KAHAN>), dim3(blocks), dim3(128), 0, s, a);
+  hipLaunchKernelGGL((region_phase<TX, TQ, R, SMAX, KAHAN>), dim3(l.blocks), dim3(128), 0, s, a,
+                     l.cy, l.cx, l.ncx, l.done, l.q);
 }
 
 template <typename TX, typename TQ, bool KAHAN>
-int launch_phase_r(int R, const PhaseArgs& a, int blocks, hipStream_t s) {
+int launch_phase_r(int R, const ImageDesc& a, const PhaseLaunch& l, hipStream_t s) {
   switch (R) {
-    case 8: launch_phase<TX, TQ, 8, KAHAN>(a, blocks, s); break;
-    case 16: launch_phase<TX, TQ, 16, KAHAN>(a, blocks, s); break;
-    case 32: launch_phase<TX, TQ, 32, KAHAN>(a, blocks, s); break;
+    case 8: launch_phase<TX, TQ, 8, KAHAN>(a, l, s); break;
+    case 16: launch_phase<TX, TQ, 16, KAHAN>(a, l, s); break;
+    case 32: launch_phase<TX, TQ, 32, KAHAN>(a, l, s); break;
     default: return SMRE_EINVAL;
   }
   HIP_OK(hipGetLastError());
   return SMRE_OK;
 }
 
-int launch_phase_any(smre_dtype dt, int inc, int kahan, int R, const PhaseArgs& a, int blocks,
-                     hipStream_t s) {
-  if (dt == SMRE_F64) return launch_phase_r<double, double, false>(R, a, blocks, s);
+int launch_phase_any(smre_dtype dt, int inc, int kahan, int R, const ImageDesc& a,
+                     const PhaseLaunch& l, hipStream_t s) {
+  if (dt == SMRE_F64) return launch_phase_r<double, double, false>(R, a, l, s);
   if (inc == SMRE_INC_BF16)
-    return kahan ? launch_phase_r<float, bf16_t, true>(R, a, blocks, s)
-                 : launch_phase_r<float, bf16_t, false>(R, a, blocks, s);
-  return kahan ? launch_phase_r<float, float, true>(R, a, blocks, s)
-               : launch_phase_r<float, float, false>(R, a, blocks, s);
+    return kahan ? launch_phase_r<float, bf16_t, true>(R, a, l, s)
+                 : launch_phase_r<float, bf16_t, false>(R, a, l, s);
+  return kahan ? launch_phase_r<float, float, true>(R, a, l, s)
+               : launch_phase_r<float, float, false>(R, a, l, s);
 }
 
 template <typename TX>
@@ -281,18 +300,17 @@ int project_impl(smre_ctx* c, smre_dtype dt, void* x, int64_t H, int64_t W, int6
   HIP_OK(hipMemcpyAsync(ws + pl.off_roff, pl.roff.data(), pl.roff.size() * 8,
                         hipMemcpyHostToDevice, s));
 
-  PhaseArgs a{};
+  ImageDesc a{};
   a.x = x;
   a.roff = (const int64_t*)(ws + pl.off_roff);
-  a.q = ws;
-  a.done = &c->ctrl->done;
   a.ld = ld;
+  a.q_byte = 0;
   a.H = (int)H;
   a.W = (int)W;
   a.nrx = pl.nrx;
+  a.nry = pl.nry;
   a.fr = pl.R + pl.smax - 1;
   a.nsides = pl.nsides;
-  a.kahan = p->kahan ? 1 : 0;
   a.guard = (float)p->guard_rel;
   for (int k = 0; k < pl.nsides; ++k) {
     a.sides[k] = pl.sides[k];
@@ -313,15 +331,19 @@ int project_impl(smre_ctx* c, smre_dtype dt, void* x, int64_t H, int64_t W, int6
       hipLaunchKernelGGL((snapshot_kernel<TX>), dim3(grid_rows(H)), dim3(256), 0, s,
                          (const TX*)x, ld, (int)H, (int)W, prev, c->ctrl);
     for (int color = 0; color < 4; ++color) {
-      a.cy = color >> 1;
-      a.cx = color & 1;
-      const int ny = (pl.nry - a.cy + 1) / 2, nx = (pl.nrx - a.cx + 1) / 2;
-      a.ncx = nx;
+      PhaseLaunch l;
+      l.cy = color >> 1;
+      l.cx = color & 1;
+      const int ny = (pl.nry - l.cy + 1) / 2, nx = (pl.nrx - l.cx + 1) / 2;
+      l.ncx = nx;
+      l.blocks = ny * nx;
+      l.done = &c->ctrl->done;
+      l.q = ws;
       if (ny <= 0 || nx <= 0) continue;
       int slot;
       rc = timing_begin(c, tacc, s, &slot);
       if (rc) return rc;
-      rc = launch_phase_any(dt, p->inc, p->kahan, pl.R, a, ny * nx, s);
+      rc = launch_phase_any(dt, p->inc, p->kahan, pl.R, a, l, s);
       if (rc) return rc;
       rc = timing_end(c, tacc, s, slot);
       if (rc) return rc;
@@ -449,6 +471,439 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int K, cons
   return SMRE_OK;
 }
 
+// ---------------------------------------------------------------- batches
+struct BatchPlan {
+  int R = 16;
+  int n = 0;
+  std::vector<Plan> plans;
+  std::vector<size_t> qoff;       // byte offset of each image's increments
+  std::vector<size_t> roff_off;   // element offset of each image's region table
+  std::vector<int64_t> prev_off;  // element offset of each image's snapshot
+  size_t qbytes = 0, roff_elems = 0, prev_elems = 0;
+  int nitems[4] = {0, 0, 0, 0};
+  size_t off_roff = 0, off_desc = 0, off_ctl = 0, off_items = 0, off_cnt = 0, off_prev = 0,
+         total = 0;
+};
+
+int plan_batch(smre_dtype dt, int n, const smre_batch_image* im, const smre_batch_params* bp,
+               int R, BatchPlan* B, bool need_offsets) {
+  B->R = R;
+  B->n = n;
+  B->plans.assign(n, Plan());
+  B->qoff.assign(n, 0);
+  B->roff_off.assign(n, 0);
+  B->prev_off.assign(n, 0);
+  B->qbytes = B->roff_elems = B->prev_elems = 0;
+  for (int c = 0; c < 4; ++c) B->nitems[c] = 0;
+  const size_t xs = dt == SMRE_F64 ? 8 : 4;
+  int64_t items_total = 0;
+  for (int i = 0; i < n; ++i) {
+    smre_params p{};
+    p.n_sides = im[i].n_sides;
+    p.sides = im[i].sides;
+    p.radius2 = im[i].radius2;
+    p.tol = im[i].tol;
+    p.max_sweeps = im[i].max_sweeps;
+    p.check_every = bp->check_every;
+    p.region = R;
+    p.inc = bp->inc;
+    p.kahan = bp->kahan;
+    p.guard_rel = bp->guard_rel;
+    if (!im[i].x || im[i].ld < im[i].W) return SMRE_EINVAL;
+    int rc = plan_project(dt, im[i].H, im[i].W, &p, &B->plans[i], need_offsets);
+    if (rc) return rc;
+    B->qoff[i] = B->qbytes;
+    B->qbytes += align_up(B->plans[i].qbytes, 256);
+    B->roff_off[i] = B->roff_elems;
+    B->roff_elems += (size_t)B->plans[i].nry * B->plans[i].nrx + 1;
+    B->prev_off[i] = (int64_t)B->prev_elems;
+    B->prev_elems += (size_t)(im[i].H * im[i].W);
+    const Plan& pl = B->plans[i];
+    for (int ry = 0; ry < pl.nry; ++ry)
+      for (int rx = 0; rx < pl.nrx; ++rx) B->nitems[(ry & 1) * 2 + (rx & 1)]++;
+    items_total += (int64_t)pl.nry * pl.nrx;
+  }
+  B->off_roff = B->qbytes;
+  B->off_desc = align_up(B->off_roff + B->roff_elems * 8, 256);
+  B->off_ctl = align_up(B->off_desc + sizeof(ImageDesc) * n, 256);
+  B->off_items = align_up(B->off_ctl + sizeof(BatchCtl) * n, 256);
+  B->off_cnt = align_up(B->off_items + sizeof(WorkItem) * items_total, 256);
+  B->off_prev = align_up(B->off_cnt + 64, 256);
+  B->total = align_up(B->off_prev + B->prev_elems * xs, 256);
+  return SMRE_OK;
+}
+
+template <typename TX, typename TQ, int R, bool KAHAN>
+int batch_grid(int cus, int want) {
+  int occ = 0;
+  HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &occ, (const void*)region_phase_batch<TX, TQ, R, R + 1, KAHAN>, 128, 0));
+  return std::max(1, std::min(want, std::max(1, occ) * cus));
+}
+
+template <typename TX, typename TQ, bool KAHAN>
+int launch_batch_phase(int R, int grid, const ImageDesc* d, const BatchCtl* ctl,
+                       const WorkItem* items, const int* cnt, unsigned char* q, hipStream_t s) {
+  switch (R) {
+    case 8:
+      hipLaunchKernelGGL((region_phase_batch<TX, TQ, 8, 9, KAHAN>), dim3(grid), dim3(128), 0, s, d,
+                         ctl, items, cnt, q);
+      break;
+    case 16:
+      hipLaunchKernelGGL((region_phase_batch<TX, TQ, 16, 17, KAHAN>), dim3(grid), dim3(128), 0, s,
+                         d, ctl, items, cnt, q);
+      break;
+    case 32:
+      hipLaunchKernelGGL((region_phase_batch<TX, TQ, 32, 33, KAHAN>), dim3(grid), dim3(128), 0, s,
+                         d, ctl, items, cnt, q);
+      break;
+    default: return SMRE_EINVAL;
+  }
+  HIP_OK(hipGetLastError());
+  return SMRE_OK;
+}
+
+template <typename TX, typename TQ, bool KAHAN>
+int grid_for_batch(smre_ctx* c, int R, int want) {
+  switch (R) {
+    case 8: return batch_grid<TX, TQ, 8, KAHAN>(c->cus, want);
+    case 16: return batch_grid<TX, TQ, 16, KAHAN>(c->cus, want);
+    default: return batch_grid<TX, TQ, 32, KAHAN>(c->cus, want);
+  }
+}
+
+// Everything one batched sweep needs, already on the device.
+struct BatchDev {
+  ImageDesc* desc;
+  BatchCtl* ctl;
+  WorkItem* items[4];
+  int* cnt;       // cnt[0..3] items per colour, cnt[4] sweeps done, cnt[5] active images
+  unsigned char* q;
+  void* prev;
+  int grid[4];
+  int n;
+  int maxh;
+};
+
+template <typename TX>
+int enqueue_batch_sweep(smre_dtype dt, const smre_batch_params* bp, int R, const BatchDev& D,
+                        bool check, hipStream_t s) {
+  (void)dt;
+  const dim3 cg(std::max(1, std::min(64, D.maxh)), D.n);
+  if (check)
+    hipLaunchKernelGGL((snapshot_batch<TX>), cg, dim3(256), 0, s, D.desc, D.ctl, (TX*)D.prev);
+  for (int color = 0; color < 4; ++color) {
+    int rc;
+    if (sizeof(TX) == 8)
+      rc = launch_batch_phase<double, double, false>(R, D.grid[color], D.desc, D.ctl,
+                                                     D.items[color], D.cnt + color, D.q, s);
+    else if (bp->inc == SMRE_INC_BF16)
+      rc = bp->kahan ? launch_batch_phase<float, bf16_t, true>(R, D.grid[color], D.desc, D.ctl,
+                                                                D.items[color], D.cnt + color, D.q, s)
+                     : launch_batch_phase<float, bf16_t, false>(R, D.grid[color], D.desc, D.ctl,
+                                                                 D.items[color], D.cnt + color, D.q, s);
+    else
+      rc = bp->kahan ? launch_batch_phase<float, float, true>(R, D.grid[color], D.desc, D.ctl,
+                                                               D.items[color], D.cnt + color, D.q, s)
+                     : launch_batch_phase<float, float, false>(R, D.grid[color], D.desc, D.ctl,
+                                                                D.items[color], D.cnt + color, D.q, s);
+    if (rc) return rc;
+  }
+  if (check)
+    hipLaunchKernelGGL((delta_batch<TX>), cg, dim3(256), 0, s, D.desc, D.ctl, (const TX*)D.prev);
+  hipLaunchKernelGGL(decide_batch, dim3(1), dim3(256), 0, s, D.ctl, D.n, check ? 1 : 0, D.cnt + 4);
+  HIP_OK(hipGetLastError());
+  return SMRE_OK;
+}
+
+// Upload descriptors, control blocks and work lists for region side R; zero
+// the increments.  Host staging lives in `host` until the stream is synced.
+template <typename TX>
+int batch_setup(smre_ctx* c, smre_dtype dt, int n, const smre_batch_image* im,
+                const smre_batch_params* bp, const BatchPlan& B, unsigned char* ws,
+                std::vector<unsigned char>& host, BatchDev* D, hipStream_t s) {
+  (void)c;
+  const size_t es = (bp->inc == SMRE_INC_BF16) ? 2 : sizeof(TX);
+  (void)es;
+  int64_t items_total = 0;
+  for (int c2 = 0; c2 < 4; ++c2) items_total += B.nitems[c2];
+  host.assign(B.off_prev - B.off_roff, 0);
+  unsigned char* h = host.data();
+  int64_t* roff = (int64_t*)(h + 0);
+  ImageDesc* desc = (ImageDesc*)(h + (B.off_desc - B.off_roff));
+  BatchCtl* ctl = (BatchCtl*)(h + (B.off_ctl - B.off_roff));
+  WorkItem* items = (WorkItem*)(h + (B.off_items - B.off_roff));
+  int* cnt = (int*)(h + (B.off_cnt - B.off_roff));
+  int64_t base[4] = {0, B.nitems[0], B.nitems[0] + B.nitems[1],
+                     B.nitems[0] + B.nitems[1] + B.nitems[2]};
+  int64_t fill[4] = {0, 0, 0, 0};
+  D->maxh = 1;
+  for (int i = 0; i < n; ++i) {
+    const Plan& pl = B.plans[i];
+    for (size_t k = 0; k < pl.roff.size(); ++k) roff[B.roff_off[i] + k] = pl.roff[k];
+    ImageDesc& a = desc[i];
+    a.x = im[i].x;
+    a.roff = (const int64_t*)(ws + B.off_roff) + B.roff_off[i];
+    a.ld = im[i].ld;
+    a.q_byte = (int64_t)B.qoff[i];
+    a.H = (int)im[i].H;
+    a.W = (int)im[i].W;
+    a.nrx = pl.nrx;
+    a.nry = pl.nry;
+    a.fr = pl.R + pl.smax - 1;
+    a.nsides = pl.nsides;
+    a.guard = (float)bp->guard_rel;
+    for (int k = 0; k < pl.nsides; ++k) {
+      a.sides[k] = pl.sides[k];
+      a.r2f[k] = (float)pl.r2[k];
+      a.rf[k] = (float)std::sqrt(pl.r2[k]);
+      a.r2d[k] = pl.r2[k];
+    }
+    BatchCtl& cl = ctl[i];
+    cl.done = 0;
+    cl.done_sweep = 0;
+    cl.converged = 0;
+    cl.max_sweeps = im[i].max_sweeps;
+    cl.delta_key = 0;
+    cl.last_delta = -1.0;
+    cl.tol = im[i].tol;
+    cl.prev_off = B.prev_off[i];
+    for (int ry = 0; ry < pl.nry; ++ry)
+      for (int rx = 0; rx < pl.nrx; ++rx) {
+        const int col = (ry & 1) * 2 + (rx & 1);
+        items[base[col] + fill[col]++] = WorkItem{i, ry * pl.nrx + rx};
+      }
+    D->maxh = std::max(D->maxh, (int)im[i].H);
+  }
+  for (int c2 = 0; c2 < 4; ++c2) cnt[c2] = B.nitems[c2];
+  cnt[4] = 0;
+  cnt[5] = n;
+  HIP_OK(hipMemcpyAsync(ws + B.off_roff, h, host.size(), hipMemcpyHostToDevice, s));
+  const int64_t nwords = (int64_t)(B.qbytes / 4);
+  hipLaunchKernelGGL((fill_kernel<uint32_t>), dim3(grid_for(nwords)), dim3(256), 0, s,
+                     (uint32_t*)ws, nwords, 0u);
+  HIP_OK(hipGetLastError());
+  D->desc = (ImageDesc*)(ws + B.off_desc);
+  D->ctl = (BatchCtl*)(ws + B.off_ctl);
+  for (int c2 = 0; c2 < 4; ++c2) D->items[c2] = (WorkItem*)(ws + B.off_items) + base[c2];
+  D->cnt = (int*)(ws + B.off_cnt);
+  D->q = ws;
+  D->prev = ws + B.off_prev;
+  D->n = n;
+  for (int c2 = 0; c2 < 4; ++c2) {
+    int g;
+    if (sizeof(TX) == 8) g = grid_for_batch<double, double, false>(c, B.R, B.nitems[c2]);
+    else if (bp->inc == SMRE_INC_BF16) g = grid_for_batch<float, bf16_t, true>(c, B.R, B.nitems[c2]);
+    else g = grid_for_batch<float, float, true>(c, B.R, B.nitems[c2]);
+    if (bp->grid > 0) g = std::min(bp->grid, std::max(1, B.nitems[c2]));
+    D->grid[c2] = std::max(1, g);
+  }
+  return SMRE_OK;
+}
+
+int batch_validate(smre_dtype dt, int n, const smre_batch_image* im, const smre_batch_params* bp,
+                   int* smax) {
+  if (n < 1 || !im || !bp) return SMRE_EINVAL;
+  if (dt != SMRE_F32 && dt != SMRE_F64) return SMRE_EINVAL;
+  if (bp->check_every < 1 || bp->grid < 0) return SMRE_EINVAL;
+  if (bp->region != 0 && bp->region != 8 && bp->region != 16 && bp->region != 32)
+    return SMRE_EINVAL;
+  *smax = 0;
+  for (int i = 0; i < n; ++i) {
+    if (im[i].n_sides < 1 || !im[i].sides) return SMRE_EINVAL;
+    for (int k = 0; k < im[i].n_sides; ++k) *smax = std::max(*smax, im[i].sides[k]);
+  }
+  return SMRE_OK;
+}
+
+std::vector<int> region_candidates(int smax, int requested) {
+  if (requested) return {requested};
+  std::vector<int> v;
+  for (int R : {8, 16, 32})
+    if (R >= smax - 1) v.push_back(R);
+  if (v.size() > 2) v.resize(2);
+  return v;
+}
+
+// Workspace of a batch: the largest layout over the tuner's candidates, then
+// (when there is more than one candidate) room to save the inputs while the
+// tuner runs.  *tune_off receives the start of that room.
+size_t batch_bytes(smre_dtype dt, int n, const smre_batch_image* im, const smre_batch_params* bp,
+                   int smax, size_t* tune_off) {
+  size_t best = 0, prev = 0;
+  const std::vector<int> cands = region_candidates(smax, bp->region);
+  for (int R : cands) {
+    BatchPlan B;
+    if (plan_batch(dt, n, im, bp, R, &B, false)) return 0;
+    best = std::max(best, B.total);
+    prev = B.prev_elems * (dt == SMRE_F64 ? 8 : 4);
+  }
+  best = align_up(best, 256);
+  if (tune_off) *tune_off = best;
+  return cands.size() > 1 ? best + align_up(prev, 256) : best;
+}
+
+template <typename TX>
+int batch_impl(smre_ctx* c, smre_dtype dt, int n, const smre_batch_image* im,
+               const smre_batch_params* bp, unsigned char* ws, size_t ws_bytes, hipStream_t s,
+               smre_report* reps) {
+  int smax = 0;
+  int rc = batch_validate(dt, n, im, bp, &smax);
+  if (rc) return rc;
+  // input check
+  for (int i = 0; i < n; ++i) {
+    hipLaunchKernelGGL(ctrl_reset_kernel, dim3(1), dim3(1), 0, s, c->ctrl);
+    bool bad = false;
+    rc = check_nonfinite<TX>(c, im[i].x, im[i].H, im[i].W, im[i].ld, s, &bad);
+    if (rc) return rc;
+    if (bad) return SMRE_ENONFINITE;
+  }
+  HIP_OK(hipEventRecord(c->t0, s));
+  // region side: requested, cached, or tuned on a scratch run of two sweeps
+  std::vector<int> cands = region_candidates(smax, bp->region);
+  char keyb[160];
+  snprintf(keyb, sizeof keyb, "dt%d inc%d k%d smax%d n%d", (int)dt, bp->inc, bp->kahan, smax, n);
+  std::string key(keyb);
+  int R = cands[0];
+  std::vector<unsigned char> host;
+  BatchPlan B;
+  BatchDev D;
+  if (cands.size() > 1 && c->tuned.count(key)) {
+    R = c->tuned[key];
+  } else if (cands.size() > 1) {
+    // save the inputs, time two sweeps per candidate, restore
+    size_t tune_off = 0;
+    if (batch_bytes(dt, n, im, bp, smax, &tune_off) > ws_bytes) return SMRE_ENOMEM;
+    std::vector<TX*> saved(n);
+    size_t off = 0;
+    for (int i = 0; i < n; ++i) {
+      saved[i] = (TX*)(ws + tune_off) + off;
+      off += (size_t)(im[i].H * im[i].W);
+    }
+    float best = 1e30f;
+    for (int Rc : cands) {
+      rc = plan_batch(dt, n, im, bp, Rc, &B, true);
+      if (rc) return rc;
+      if (B.total > ws_bytes) return SMRE_ENOMEM;
+      for (int i = 0; i < n; ++i)
+        HIP_OK(hipMemcpy2DAsync(saved[i], im[i].W * sizeof(TX), im[i].x, im[i].ld * sizeof(TX),
+                                im[i].W * sizeof(TX), im[i].H, hipMemcpyDeviceToDevice, s));
+      rc = batch_setup<TX>(c, dt, n, im, bp, B, ws, host, &D, s);
+      if (rc) return rc;
+      // the snapshot buffer holds the saved inputs: sweep without checks
+      hipEvent_t e0 = c->ev[0], e1 = c->ev[1];
+      HIP_OK(hipEventRecord(e0, s));
+      for (int k = 0; k < 2; ++k) {
+        rc = enqueue_batch_sweep<TX>(dt, bp, Rc, D, false, s);
+        if (rc) return rc;
+      }
+      HIP_OK(hipEventRecord(e1, s));
+      HIP_OK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+      for (int i = 0; i < n; ++i)
+        HIP_OK(hipMemcpy2DAsync(im[i].x, im[i].ld * sizeof(TX), saved[i], im[i].W * sizeof(TX),
+                                im[i].W * sizeof(TX), im[i].H, hipMemcpyDeviceToDevice, s));
+      if (ms < best) {
+        best = ms;
+        R = Rc;
+      }
+    }
+    c->tuned[key] = R;
+  }
+  rc = plan_batch(dt, n, im, bp, R, &B, true);
+  if (rc) return rc;
+  if (B.total > ws_bytes) return SMRE_ENOMEM;
+  rc = batch_setup<TX>(c, dt, n, im, bp, B, ws, host, &D, s);
+  if (rc) return rc;
+
+  int max_sw = 0;
+  for (int i = 0; i < n; ++i) max_sw = std::max(max_sw, im[i].max_sweeps);
+  // capture one plain and one checking sweep
+  hipGraphExec_t gx[2] = {nullptr, nullptr};
+  hipGraph_t gr[2] = {nullptr, nullptr};
+  if (bp->use_graph) {
+    HIP_OK(hipStreamSynchronize(s));
+    for (int g = 0; g < 2; ++g) {
+      HIP_OK(hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
+      int rc2 = enqueue_batch_sweep<TX>(dt, bp, R, D, g == 1, c->capture);
+      hipGraph_t graph = nullptr;
+      HIP_OK(hipStreamEndCapture(c->capture, &graph));
+      if (rc2) return rc2;
+      gr[g] = graph;
+      HIP_OK(hipGraphInstantiate(&gx[g], graph, nullptr, nullptr, 0));
+    }
+  }
+  TimingAcc tacc;
+  std::deque<std::pair<int, int>> inflight;
+  int lag_slot = 0;
+  bool host_done = false;
+  for (int sweep = 1; sweep <= max_sw && !host_done; ++sweep) {
+    const bool check = (sweep % bp->check_every == 0);
+    int slot;
+    rc = timing_begin(c, tacc, s, &slot);
+    if (rc) return rc;
+    if (bp->use_graph) {
+      HIP_OK(hipGraphLaunch(gx[check ? 1 : 0], s));
+    } else {
+      rc = enqueue_batch_sweep<TX>(dt, bp, R, D, check, s);
+      if (rc) return rc;
+    }
+    rc = timing_end(c, tacc, s, slot);
+    if (rc) return rc;
+    HIP_OK(hipMemcpyAsync(c->counters_host + 2 * lag_slot, D.cnt + 4, 2 * sizeof(int),
+                          hipMemcpyDeviceToHost, s));
+    HIP_OK(hipEventRecord(c->lag_ev[lag_slot], s));
+    inflight.push_back({lag_slot, sweep});
+    lag_slot = (lag_slot + 1) % (kLag + 1);
+    if ((int)inflight.size() > kLag) {
+      auto f = inflight.front();
+      inflight.pop_front();
+      HIP_OK(hipEventSynchronize(c->lag_ev[f.first]));
+      if (c->counters_host[2 * f.first + 1] == 0) host_done = true;
+    }
+  }
+  HIP_OK(hipStreamSynchronize(s));
+  rc = timing_flush(c, tacc, true);
+  if (rc) return rc;
+  for (int g = 0; g < 2; ++g) {
+    if (gx[g]) (void)hipGraphExecDestroy(gx[g]);
+    if (gr[g]) (void)hipGraphDestroy(gr[g]);
+  }
+  std::vector<BatchCtl> ctl(n);
+  HIP_OK(hipMemcpy(ctl.data(), D.ctl, sizeof(BatchCtl) * n, hipMemcpyDeviceToHost));
+  HIP_OK(hipEventRecord(c->t1, s));
+  HIP_OK(hipEventSynchronize(c->t1));
+  float ms = 0.f;
+  HIP_OK(hipEventElapsedTime(&ms, c->t0, c->t1));
+  bool all_conv = true;
+  for (int i = 0; i < n; ++i) {
+    const Plan& pl = B.plans[i];
+    const int sw = ctl[i].done ? ctl[i].done_sweep : max_sw;
+    if (im[i].tol > 0 && !ctl[i].converged) all_conv = false;
+    if (reps) {
+      smre_report& r = reps[i];
+      double viol = 0.0;
+      rc = run_violation<TX>(c, im[i].x, im[i].H, im[i].W, im[i].ld, pl.nsides, pl.sides, pl.r2,
+                             s, &viol);
+      if (rc) return rc;
+      const size_t es = (bp->inc == SMRE_INC_BF16) ? 2 : sizeof(TX);
+      r.sweeps = sw;
+      r.converged = ctl[i].converged;
+      r.region = R;
+      r.inner_sweeps = 0;
+      r.last_delta = ctl[i].last_delta;
+      r.max_violation = viol;
+      r.elapsed_ms = ms;
+      r.kernel_ms = tacc.ms;
+      r.kernel_launches = tacc.launches;
+      r.bytes_moved = (double)sw * (2.0 * es * (double)pl.nq + 2.0 * sizeof(TX) * (double)(im[i].H * im[i].W));
+      r.window_projections = (double)sw * (double)pl.nwin;
+    }
+  }
+  return all_conv ? SMRE_OK : SMRE_NOT_CONVERGED;
+}
+
 // ---------------------------------------------------------------- bounds
 // Regularised lower incomplete gamma P(a, x): power series for x < a + 1,
 // continued fraction (modified Lentz) for the complement otherwise.
@@ -554,6 +1009,8 @@ void smre_ctx_destroy(smre_ctx* c) {
     if (e) (void)hipEventDestroy(e);
   if (c->t0) (void)hipEventDestroy(c->t0);
   if (c->t1) (void)hipEventDestroy(c->t1);
+  if (c->counters_host) (void)hipHostFree(c->counters_host);
+  if (c->capture) (void)hipStreamDestroy(c->capture);
   delete c;
 }
 
@@ -646,6 +1103,47 @@ int smre_dykstra_incomplete(smre_ctx* c, smre_dtype dt, void* x, int64_t H, int6
   if (dt == SMRE_F64)
     return icd_impl<double>(c, x, H, W, ld, K, r2, tol, mode, max_inner, nph, s, rep);
   return icd_impl<float>(c, x, H, W, ld, K, r2, tol, mode, max_inner, nph, s, rep);
+}
+
+int smre_batch_workspace_size(smre_dtype dt, int32_t n, const smre_batch_image* im,
+                              const smre_batch_params* bp, size_t* bytes) {
+  if (!bytes) return SMRE_EINVAL;
+  int smax = 0;
+  int rc = batch_validate(dt, n, im, bp, &smax);
+  if (rc) return rc;
+  *bytes = batch_bytes(dt, n, im, bp, smax, nullptr);
+  return *bytes ? SMRE_OK : SMRE_EINVAL;
+}
+
+int smre_dykstra_project_batch(smre_ctx* c, smre_dtype dt, int32_t n, const smre_batch_image* im,
+                               const smre_batch_params* bp, void* workspace, size_t ws_bytes,
+                               void* stream, smre_report* reps) {
+  if (!c) return SMRE_EINVAL;
+  size_t need = 0;
+  int rc = smre_batch_workspace_size(dt, n, im, bp, &need);
+  if (rc) return rc;
+  rc = set_device(c);
+  if (rc) return rc;
+  unsigned char* ws = (unsigned char*)workspace;
+  if (ws) {
+    if (ws_bytes < need) return SMRE_ENOMEM;
+  } else {
+    if (c->ws_bytes < need) {
+      if (c->ws) HIP_OK(hipFree(c->ws));
+      c->ws = nullptr;
+      c->ws_bytes = 0;
+      if (hipMalloc(&c->ws, need) != hipSuccess) {
+        (void)hipGetLastError();
+        return SMRE_ENOMEM;
+      }
+      c->ws_bytes = need;
+    }
+    ws = (unsigned char*)c->ws;
+    ws_bytes = c->ws_bytes;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if (dt == SMRE_F64) return batch_impl<double>(c, dt, n, im, bp, ws, ws_bytes, s, reps);
+  return batch_impl<float>(c, dt, n, im, bp, ws, ws_bytes, s, reps);
 }
 
 int smre_max_violation(smre_ctx* c, smre_dtype dt, const void* x, int64_t H, int64_t W,

@@ -1,0 +1,125 @@
+"""GPU batches: images of different sizes in one persistent launch per colour.
+
+Each image of a batch receives exactly the arithmetic it receives alone with
+the same region side, so the checks are: per sweep against the oracle's
+region order (FP64, 1e-12), bitwise equality with single-image runs (alone vs
+in the mix, including the sweep at which each image stops), graph replay vs
+direct launches, and the tuner's choice being a valid region side.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import smre_inputs as gi
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def smre():
+    import paper_1503_03492_amd as m
+    assert torch.cuda.is_available()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(smre):
+    c = smre.Context(0)
+    yield c
+    c.close()
+
+
+SHAPES = [(40, 52), (64, 64), (33, 90), (96, 128), (17, 17)]
+
+
+def images(dtype=np.float64, seed=0):
+    out = []
+    for k, (H, W) in enumerate(SHAPES):
+        out.append(gi.emitters(H, W, n_e=max(2, H * W // 300), seed=seed + k).astype(dtype))
+    return out
+
+
+def dev(a, dt):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype=dt)
+
+
+@pytest.mark.parametrize("R", [8, 16])
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_per_sweep_matches_oracle(ctx, R, graph):
+    sides = list(range(1, 9))
+    r2 = oracle.chi2_bounds(sides)
+    x0s = images()
+    xs = [dev(x, torch.float64) for x in x0s]
+    rc, reps = ctx.project_batch(xs, sides, r2, tol=0, max_sweeps=3, region=R, use_graph=graph)
+    for x0, x, rep in zip(x0s, xs, reps):
+        ref, _, _ = oracle.dykstra(x0, sides, r2, tol=0, max_sweeps=3,
+                                   order=oracle.ORDER_REGION, region=R)
+        z = x.cpu().numpy()
+        assert rep["sweeps"] == 3 and rep["region"] == R
+        assert np.max(np.abs(z - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+def test_batch_equals_single_bitwise(ctx, dt):
+    """Alone vs in the mix: same bits and the same stopping sweep per image."""
+    sides = list(range(1, 9))
+    r2 = oracle.chi2_bounds(sides)
+    x0s = images(np.float32)
+    tols = [1e-4, 1e-5, 1e-4, 1e-5, 1e-6]
+    xs = [dev(x, dt) for x in x0s]
+    rc, reps = ctx.project_batch(xs, sides, r2, tol=tols, max_sweeps=4000, region=16)
+    for x0, x, rep, tol in zip(x0s, xs, reps, tols):
+        y = dev(x0, dt)
+        rc1, rep1 = ctx.project(y, sides, r2, tol=tol, max_sweeps=4000, region=16)
+        assert rep["sweeps"] == rep1["sweeps"] and rep["converged"] == rep1["converged"]
+        assert torch.equal(x, y)
+
+
+def test_batch_per_image_sides(ctx):
+    x0s = images()
+    sides_l = [[1, 2, 3], list(range(1, 9)), [2, 5], [1, 4, 7, 9], [1]]
+    r2_l = [oracle.chi2_bounds(s) for s in sides_l]
+    xs = [dev(x, torch.float64) for x in x0s]
+    ctx.project_batch(xs, sides_l, r2_l, tol=0, max_sweeps=2, region=16)
+    for x0, x, s, r in zip(x0s, xs, sides_l, r2_l):
+        ref, _, _ = oracle.dykstra(x0, s, r, tol=0, max_sweeps=2, order=oracle.ORDER_REGION,
+                                   region=16)
+        assert np.max(np.abs(x.cpu().numpy() - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_batch_autotune_picks_valid_region(ctx):
+    sides = list(range(1, 9))
+    r2 = oracle.chi2_bounds(sides)
+    x0s = images()
+    xs = [dev(x, torch.float64) for x in x0s]
+    rc, reps = ctx.project_batch(xs, sides, r2, tol=0, max_sweeps=2, region=0)
+    R = reps[0]["region"]
+    assert R in (8, 16)
+    for x0, x in zip(x0s, xs):
+        ref, _, _ = oracle.dykstra(x0, sides, r2, tol=0, max_sweeps=2,
+                                   order=oracle.ORDER_REGION, region=R)
+        assert np.max(np.abs(x.cpu().numpy() - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_batch_caps_and_status(ctx, smre):
+    sides = list(range(1, 9))
+    r2 = oracle.chi2_bounds(sides)
+    xs = [dev(x, torch.float32) for x in images(np.float32)]
+    rc, reps = ctx.project_batch(xs, sides, r2, tol=1e-9, max_sweeps=[2, 3, 4, 5, 6], region=16)
+    assert rc == smre.NOT_CONVERGED
+    assert [r["sweeps"] for r in reps] == [2, 3, 4, 5, 6]
+
+
+def test_batch_uneven_full_size_sample(ctx):
+    """Batched uneven sizes (sides drawn from {128..768}, 1 emitter / 1300 px^2),
+    three sweeps: sampled images equal their single-image runs bitwise."""
+    x0s = [x.astype(np.float32) for x in gi.batch_images(n=16, seed=0)]
+    sides = list(range(1, 9))
+    r2 = oracle.chi2_bounds(sides)
+    xs = [dev(x, torch.float32) for x in x0s]
+    ctx.project_batch(xs, sides, r2, tol=0, max_sweeps=3, region=16)
+    for k in (0, 7, 15):
+        y = dev(x0s[k], torch.float32)
+        ctx.project(y, sides, r2, tol=0, max_sweeps=3, region=16)
+        assert torch.equal(xs[k], y)
