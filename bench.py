@@ -64,6 +64,167 @@ def cpu_baseline(x0, sides, r2, budget_s=15.0):
                       f"{el:.1f} s, single thread"}
 
 
+def bench_batch(args):
+    """64 images, sides drawn from {128,...,768}, 1 emitter per 1300 px^2, window
+    sides 1..8, FP32, FP64 checks, tol 1e-5: one persistent launch per colour."""
+    import torch
+
+    import paper_1503_03492_amd as smre
+    import smre_inputs as gi
+    x0s = [x.astype(np.float32) for x in gi.batch_images(n=args.batch_n, seed=0)]
+    sides = list(range(1, 9))
+    r2 = smre.chi2_bounds(sides)
+    devs = [torch.from_numpy(x).cuda() for x in x0s]
+    xs = [torch.empty_like(d) for d in devs]
+    ctx = smre.Context(0)
+    ctx.set_timing(True)
+
+    def step():
+        for x, d in zip(xs, devs):
+            x.copy_(d)
+        return ctx.project_batch(xs, sides, r2, tol=1e-5, max_sweeps=6000, region=args.region)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = []
+    for _ in range(args.steps):
+        rc, rr = step()
+        reps.append(rr)
+        print(f"step: max sweeps {max(r['sweeps'] for r in rr)}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    wp = sum(r["window_projections"] for rr in reps for r in rr)
+    by = sum(r["bytes_moved"] for rr in reps for r in rr)
+    sweeps = [r["sweeps"] for r in reps[-1]]
+    kms = reps[-1][0]["kernel_ms"]
+    out = {"metric": "window projections/s (batched full Dykstra to tol, 64 uneven images)",
+           "value": wp / el, "unit": "window projections/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "batch64_uneven_128-768_sides1-8_fp32", "images": len(x0s),
+                      "tol": 1e-5, "region": reps[-1][0]["region"]},
+           "sweeps_min_max": [min(sweeps), max(sweeps)],
+           "achieved_GBps_alg": by / el / 1e9, "sweep_graph_ms_total": kms}
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """Poisson arrivals (rate args.rate) of emitter images with log-uniform side in
+    [256, 1024], window sides 1..max(8, side/64), tol 1e-5, FP32 through the
+    continuous-batching server; then the same trace through plain per-image
+    FP64 solves on the same GPU, first-in first-out."""
+    import threading
+
+    import torch
+
+    import paper_1503_03492_amd as smre
+    import smre_inputs as gi
+    times, sides_px, kids = gi.serve_trace(args.serve_n, rate=args.rate, seed=0)
+    imgs = [gi.serve_image(s, k).astype(np.float32) for s, k in zip(sides_px, kids)]
+    wsides = [gi.serve_sides(s) for s in sides_px]
+    bounds = [smre.chi2_bounds(w) for w in wsides]
+    srv = smre.Server(max_active=args.max_active, queue_cap=100000)
+    lat = [None] * len(imgs)
+    done_at = [None] * len(imgs)
+    tickets = [None] * len(imgs)
+    t_start = time.perf_counter()
+
+    def submitter():
+        for i, (t, x) in enumerate(zip(times, imgs)):
+            d = t - (time.perf_counter() - t_start)
+            if d > 0:
+                time.sleep(d)
+            tickets[i] = srv.submit(x, wsides[i], bounds[i], tol=1e-5, max_sweeps=6000)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    pending = set(range(len(imgs)))
+    while pending:
+        for i in list(pending):
+            if tickets[i] is None:
+                continue
+            r = srv.poll(tickets[i], imgs[i].shape)
+            if r is not None:
+                lat[i] = r[3]
+                done_at[i] = time.perf_counter() - t_start
+                pending.discard(i)
+                if len(pending) % 10 == 0:
+                    print(f"served {len(imgs) - len(pending)}", file=sys.stderr, flush=True)
+        time.sleep(0.001)
+    th.join()
+    span = max(done_at)
+    srv.close()
+    res = {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+           "throughput_req_s": len(imgs) / span, "requests": len(imgs),
+           "offered_rate_req_s": args.rate}
+    # baseline: the same trace, one FP64 solve at a time
+    base_lat = []
+    if args.serve_baseline:
+        ctx = smre.Context(0)
+        clock = 0.0
+        for i, x in enumerate(imgs):
+            xd = torch.from_numpy(x.astype(np.float64)).cuda()
+            start = max(clock, times[i])
+            t0 = time.perf_counter()
+            ctx.project(xd, wsides[i], bounds[i], tol=1e-5, max_sweeps=6000)
+            torch.cuda.synchronize()
+            clock = start + (time.perf_counter() - t0)
+            base_lat.append(clock - times[i])
+            print(f"baseline {i + 1}/{len(imgs)}", file=sys.stderr, flush=True)
+        res["baseline_fp64_fifo"] = {"p50_s": float(np.percentile(base_lat, 50)),
+                                     "p99_s": float(np.percentile(base_lat, 99)),
+                                     "throughput_req_s": len(imgs) / clock}
+    out = {"metric": "p50/p99 serve latency and throughput (continuous batching)",
+           "value": res["throughput_req_s"], "unit": "requests/s", "n_gpus": 1, "steps": 1,
+           "warmup": 0, "ms_per_step": span * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "serve_poisson_256-1024_sides1-max(8,side/64)_tol1e-5",
+                      "max_active": args.max_active}, "serve": res}
+    print(json.dumps(out), flush=True)
+
+
+def bench_icd(args):
+    """The paper's incomplete Dykstra on the 1024^2 FP32 image: K = 4 (squares
+    of side 1..16), 5 phases, mean-abs inner tolerance 1e-3 (the paper's)."""
+    import torch
+
+    import paper_1503_03492_amd as smre
+    import smre_inputs as gi
+    x0 = gi.emitters(1024, 1024, n_e=2000, seed=0).astype(np.float32)
+    K = 4
+    r2 = smre.chi2_bounds([1 << k for k in range(K + 1)])
+    d = torch.from_numpy(x0).cuda()
+    x = torch.empty_like(d)
+    ctx = smre.Context(0)
+    ctx.set_timing(True)
+    for _ in range(args.warmup):
+        x.copy_(d)
+        ctx.incomplete(x, K, r2, tol=1e-3, mode=smre.TOL_MEANABS, max_inner=10000)
+    torch.cuda.synchronize()
+    reps = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        x.copy_(d)
+        reps.append(ctx.incomplete(x, K, r2, tol=1e-3, mode=smre.TOL_MEANABS, max_inner=10000))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    wp = sum(r["window_projections"] for r in reps)
+    kms = sum(r["kernel_ms"] for r in reps)
+    by = sum(r["bytes_moved"] for r in reps)
+    out = {"metric": "window projections/s (incomplete Dykstra, 1024^2 image)",
+           "value": wp / el, "unit": "window projections/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic", "config": {"workload": "icd_1024sq_K4_tol1e-3_meanabs"},
+           "inner_sweeps": reps[-1]["inner_sweeps"], "phase_kernel_ms": kms / args.steps,
+           "hbm_GBps": by / (kms * 1e-3) / 1e9 if kms else None,
+           "max_violation_full_family": reps[-1]["max_violation"]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,11 +233,23 @@ def main():
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--region", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-n", type=int, default=64)
+    ap.add_argument("--serve-n", type=int, default=40)
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--max-active", type=int, default=16)
+    ap.add_argument("--serve-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the projection of one image does not shard "
               "(see the design notes); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "c4":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
+    if args.workload == "icd":
+        return bench_icd(args)
 
     import torch
 

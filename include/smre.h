@@ -197,6 +197,50 @@ int smre_dykstra_project_batch(smre_ctx* ctx, smre_dtype dtype, int32_t n,
                                void* workspace, size_t ws_bytes, void* stream,
                                smre_report* reports);
 
+/* ---- Serving: continuous batching of projection requests ----
+ * A server owns one device, a memory arena of hbm_budget_bytes and a
+ * scheduler thread.  submit() copies the host image and returns a ticket at
+ * once; requests are admitted first-in first-out while an active slot is free
+ * and their device footprint (increments, region table, image, snapshot)
+ * fits the arena, and join the running set at the next sweep.  Each active
+ * request advances by one sweep per step (the batched kernels, region side
+ * 16, FP32 images), is checked in FP64 on its own cadence and retires when
+ * it converges or reaches its cap; its slot and memory are then reused.
+ * A request gets the same arithmetic alone or in any mix.  submit(), poll()
+ * and stats() are thread-safe. */
+typedef struct smre_server smre_server;
+typedef struct {
+  int device;
+  size_t hbm_budget_bytes;  /* arena size (0 = 80% of free device memory) */
+  int32_t max_active;       /* requests on the device at once */
+  int32_t queue_cap;        /* queued requests beyond which submit returns SMRE_EBUSY */
+  int32_t inc;              /* smre_inc */
+  int32_t kahan;
+  int32_t check_every;
+  int32_t reserved;
+  double guard_rel;
+} smre_serve_config;
+
+typedef struct {
+  int64_t submitted, completed, rejected, failed, active, queued, sweeps, bytes_in_use;
+} smre_serve_counters;
+
+int smre_serve_create(const smre_serve_config* cfg, smre_server** out);
+/* Stops the scheduler; unfinished tickets are cancelled. */
+void smre_serve_destroy(smre_server* s);
+/* x_host: H x W row-major FP32 (copied before return).  p: sides, radius2
+ * (max side 17), tol, max_sweeps; other fields come from the server config.
+ * Errors: SMRE_EINVAL, SMRE_ENONFINITE, SMRE_ETOOBIG (can never fit the
+ * arena), SMRE_EBUSY (queue full), SMRE_EDEVICE (server failed). */
+int smre_serve_submit(smre_server* s, const float* x_host, int32_t H, int32_t W,
+                      const smre_params* p, uint64_t* ticket);
+/* SMRE_PENDING while queued or running.  Otherwise the ticket is released:
+ * SMRE_OK / SMRE_NOT_CONVERGED with out_host (>= H W floats) and rep filled,
+ * or the request's error.  latency_s (may be NULL): completion - submission. */
+int smre_serve_poll(smre_server* s, uint64_t ticket, float* out_host, size_t out_elems,
+                    smre_report* rep, double* latency_s);
+int smre_serve_stats(smre_server* s, smre_serve_counters* out);
+
 /* FP64 feasibility of x (device): *out = max_S sum_S x^2 / r2_S - 1 over all
  * windows of the given sides (<= 0 means every constraint holds). */
 int smre_max_violation(smre_ctx* ctx, smre_dtype dtype, const void* x, int64_t H, int64_t W,

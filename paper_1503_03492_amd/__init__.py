@@ -62,6 +62,19 @@ class BatchParams(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("grid", ctypes.c_int32)]
 
 
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_size_t),
+                ("max_active", ctypes.c_int32), ("queue_cap", ctypes.c_int32),
+                ("inc", ctypes.c_int32), ("kahan", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("guard_rel", ctypes.c_double)]
+
+
+class ServeCounters(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "rejected", "failed",
+                                              "active", "queued", "sweeps", "bytes_in_use")]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
@@ -91,6 +104,15 @@ def _load():
     L.smre_dykstra_project_batch.argtypes = [vp, ctypes.c_int, i32, ctypes.POINTER(BatchImage),
                                              ctypes.POINTER(BatchParams), vp, ctypes.c_size_t,
                                              vp, ctypes.POINTER(Report)]
+    L.smre_serve_create.argtypes = [ctypes.POINTER(ServeConfig), ctypes.POINTER(vp)]
+    L.smre_serve_destroy.argtypes = [vp]
+    L.smre_serve_destroy.restype = None
+    L.smre_serve_submit.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32, i32,
+                                    ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_uint64)]
+    L.smre_serve_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_float),
+                                  ctypes.c_size_t, ctypes.POINTER(Report),
+                                  ctypes.POINTER(ctypes.c_double)]
+    L.smre_serve_stats.argtypes = [vp, ctypes.POINTER(ServeCounters)]
     return L
 
 
@@ -99,7 +121,8 @@ _lib = _load()
 EXPORTS = ["smre_status_string", "smre_ctx_create", "smre_ctx_destroy", "smre_ctx_set_timing",
            "smre_chi2_bounds", "smre_paper_bounds", "smre_workspace_size",
            "smre_dykstra_project", "smre_dykstra_incomplete", "smre_max_violation",
-           "smre_batch_workspace_size", "smre_dykstra_project_batch"]
+           "smre_batch_workspace_size", "smre_dykstra_project_batch", "smre_serve_create",
+           "smre_serve_destroy", "smre_serve_submit", "smre_serve_poll", "smre_serve_stats"]
 
 
 def lib():
@@ -297,3 +320,55 @@ class Context:
                                        W, ld, len(s), sp, rp, _stream(stream), ctypes.byref(out)),
                "smre_max_violation")
         return out.value
+
+
+class Server:
+    """Continuous-batching projection server (FP32 images, host in / host out)."""
+
+    def __init__(self, device=0, hbm_budget_bytes=0, max_active=16, queue_cap=1024,
+                 inc=INC_SAME, kahan=True, check_every=1, guard_rel=1e-5):
+        cfg = ServeConfig(int(device), int(hbm_budget_bytes), int(max_active), int(queue_cap),
+                          int(inc), 1 if kahan else 0, int(check_every), 0, float(guard_rel))
+        h = ctypes.c_void_p()
+        _check(_lib.smre_serve_create(ctypes.byref(cfg), ctypes.byref(h)), "smre_serve_create")
+        self._h = h
+
+    def close(self):
+        if self._h:
+            _lib.smre_serve_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, x, sides, radius2, tol=1e-5, max_sweeps=5000):
+        """x: 2-D float32 numpy array.  Returns a ticket (int) or raises SmreError."""
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        s, sp = _ivec(sides)
+        r, rp = _dvec(radius2)
+        p = Params(len(s), sp, rp, float(tol), int(max_sweeps), 1, 16, 0, 1, 0, 0.0)
+        t = ctypes.c_uint64()
+        _check(_lib.smre_serve_submit(self._h, x.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                      x.shape[0], x.shape[1], ctypes.byref(p), ctypes.byref(t)),
+               "smre_serve_submit")
+        return t.value
+
+    def poll(self, ticket, shape):
+        """None while pending; else (status, result array, report dict, latency s)."""
+        out = np.empty(shape, dtype=np.float32)
+        rep = Report()
+        lat = ctypes.c_double()
+        rc = _lib.smre_serve_poll(self._h, ctypes.c_uint64(ticket),
+                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), out.size,
+                                  ctypes.byref(rep), ctypes.byref(lat))
+        if rc == PENDING:
+            return None
+        return rc, out, rep.as_dict(), lat.value
+
+    def stats(self):
+        c = ServeCounters()
+        _check(_lib.smre_serve_stats(self._h, ctypes.byref(c)), "smre_serve_stats")
+        return {k: getattr(c, k) for k, _ in c._fields_}

@@ -49,6 +49,7 @@ struct IcdArgs {
   double tol;
   double r2[6];
   int* inner_count;   // total inner sweeps (device)
+  unsigned long long* proj_count;  // total square projections (device)
 };
 
 template <typename T, int K>
@@ -92,6 +93,16 @@ __global__ __launch_bounds__(64) void icd_phase(IcdArgs a) {
       active[k][e] = (lane * NPL + e) < NPX && sy >= 0 && sx >= 0 && sy + L <= a.H &&
                      sx + L <= a.W;
     }
+
+  // squares this block projects per inner sweep: one leader pixel per square
+  int leaders = 0;
+#pragma unroll
+  for (int k = 0; k <= K; ++k)
+#pragma unroll
+    for (int e = 0; e < NPL; ++e)
+      leaders += (k >= i && active[k][e] && ((lane * NPL + e) & ((1 << (2 * k)) - 1)) == 0);
+  float nsq = (float)leaders;
+  nsq = group_sum<64>(nsq);
 
   T q[K + 1][NPL];
 #pragma unroll
@@ -168,7 +179,10 @@ __global__ __launch_bounds__(64) void icd_phase(IcdArgs a) {
 #pragma unroll
   for (int e = 0; e < NPL; ++e)
     if (inimg[e]) xg[(int64_t)gy[e] * a.ld + gx[e]] = x[e];
-  if (lane == 0) atomicAdd(a.inner_count, it);
+  if (lane == 0) {
+    atomicAdd(a.inner_count, it);
+    atomicAdd(a.proj_count, (unsigned long long)it * (unsigned long long)(nsq + 0.5f));
+  }
 }
 
 }  // namespace smre

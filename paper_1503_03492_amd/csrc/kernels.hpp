@@ -298,6 +298,10 @@ struct BatchCtl {
   int done_sweep;                // sweep at which it was retired
   int converged;                 // 1 if the tolerance was met
   int max_sweeps;
+  int sweeps;                    // sweeps this image has run (images may join at different times)
+  int check_every;
+  int gen;                       // occupant generation (serving: tells a slot's requests apart)
+  int pad;
   unsigned long long delta_key;  // running max |x - prev| of the checked sweep
   double last_delta;
   double tol;
@@ -739,7 +743,7 @@ template <typename TX>
 __global__ __launch_bounds__(256) void snapshot_batch(const ImageDesc* __restrict__ imgs,
                                                       BatchCtl* ctl, TX* prev) {
   const int im = blockIdx.y;
-  if (ctl[im].done) return;
+  if (ctl[im].done || (ctl[im].sweeps + 1) % ctl[im].check_every != 0) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) ctl[im].delta_key = dkey(0.0);
   const ImageDesc& a = imgs[im];
   const TX* x = (const TX*)a.x;
@@ -753,7 +757,7 @@ template <typename TX>
 __global__ __launch_bounds__(256) void delta_batch(const ImageDesc* __restrict__ imgs,
                                                    BatchCtl* ctl, const TX* prev) {
   const int im = blockIdx.y;
-  if (ctl[im].done) return;
+  if (ctl[im].done || (ctl[im].sweeps + 1) % ctl[im].check_every != 0) return;
   const ImageDesc& a = imgs[im];
   const TX* x = (const TX*)a.x;
   const TX* pv = prev + ctl[im].prev_off;
@@ -776,8 +780,9 @@ __global__ __launch_bounds__(256) void decide_batch(BatchCtl* ctl, int n, int ch
   for (int im = threadIdx.x; im < n; im += blockDim.x) {
     BatchCtl& c = ctl[im];
     if (c.done) continue;
+    const int sw = ++c.sweeps;
     bool stop = false;
-    if (check) {
+    if (check && sw % c.check_every == 0) {
       const double d = dkey_inv(c.delta_key);
       c.last_delta = d;
       if (d < c.tol) {
@@ -785,10 +790,10 @@ __global__ __launch_bounds__(256) void decide_batch(BatchCtl* ctl, int n, int ch
         stop = true;
       }
     }
-    if (sweep >= c.max_sweeps) stop = true;
+    if (sw >= c.max_sweeps) stop = true;
     if (stop) {
       c.done = 1;
-      c.done_sweep = sweep;
+      c.done_sweep = sw;
     } else {
       atomicAdd(&active, 1);
     }

@@ -23,6 +23,7 @@
 
 #include "icd.hpp"
 #include "kernels.hpp"
+#include "serve_core.hpp"
 #include "smre.h"
 
 using namespace smre;
@@ -405,7 +406,7 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int K, cons
   int rc = check_nonfinite<T>(c, x, H, W, ld, s, &bad);
   if (rc) return rc;
   if (bad) return SMRE_ENONFINITE;
-  hipLaunchKernelGGL((fill_kernel<int>), dim3(1), dim3(64), 0, s, c->counter, (int64_t)1, 0);
+  hipLaunchKernelGGL((fill_kernel<int>), dim3(1), dim3(64), 0, s, c->counter, (int64_t)4, 0);
   IcdArgs a{};
   a.x = x;
   a.ld = ld;
@@ -416,6 +417,7 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int K, cons
   a.tol = tol;
   for (int k = 0; k <= K; ++k) a.r2[k] = r2[k];
   a.inner_count = c->counter;
+  a.proj_count = (unsigned long long*)(c->counter + 2);
   const int B = 1 << K;
   TimingAcc tacc;
   for (int ph = 0; ph < nph; ++ph) {
@@ -441,13 +443,16 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int K, cons
   HIP_OK(hipStreamSynchronize(s));
   rc = timing_flush(c, tacc, true);
   if (rc) return rc;
-  int inner = 0;
-  HIP_OK(hipMemcpy(&inner, c->counter, sizeof(int), hipMemcpyDeviceToHost));
+  int cnt[4] = {0, 0, 0, 0};
+  HIP_OK(hipMemcpy(cnt, c->counter, sizeof(cnt), hipMemcpyDeviceToHost));
+  const int inner = cnt[0];
+  unsigned long long proj = 0;
+  std::memcpy(&proj, cnt + 2, sizeof proj);
   std::vector<int> sides(K + 1);
   for (int k = 0; k <= K; ++k) sides[k] = 1 << k;
   double viol = 0.0;
-  // feasibility over the aligned squares of every level is not the ICD family
-  // (which is shifted); report the full-family violation of the levels' sides.
+  // Reported: the violation over the FULL family of the levels' sides (every
+  // position), i.e. how far ICD is from feasibility for the exact method.
   rc = run_violation<T>(c, x, H, W, ld, K + 1, sides.data(), r2, s, &viol);
   if (rc) return rc;
   HIP_OK(hipEventRecord(c->t1, s));
@@ -465,8 +470,7 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int K, cons
     rep->kernel_ms = tacc.ms;
     rep->kernel_launches = tacc.launches;
     rep->bytes_moved = 2.0 * sizeof(T) * (double)H * W * nph;
-    double wp = 0.0;  // window projections: squares per block x inner sweeps is data dependent
-    rep->window_projections = wp;
+    rep->window_projections = (double)proj;
   }
   return SMRE_OK;
 }
@@ -664,6 +668,8 @@ int batch_setup(smre_ctx* c, smre_dtype dt, int n, const smre_batch_image* im,
     cl.done_sweep = 0;
     cl.converged = 0;
     cl.max_sweeps = im[i].max_sweeps;
+    cl.sweeps = 0;
+    cl.check_every = bp->check_every;
     cl.delta_key = 0;
     cl.last_delta = -1.0;
     cl.tol = im[i].tol;
@@ -839,7 +845,7 @@ int batch_impl(smre_ctx* c, smre_dtype dt, int n, const smre_batch_image* im,
   int lag_slot = 0;
   bool host_done = false;
   for (int sweep = 1; sweep <= max_sw && !host_done; ++sweep) {
-    const bool check = (sweep % bp->check_every == 0);
+    const bool check = true;  // each image tests its own cadence on the device
     int slot;
     rc = timing_begin(c, tacc, s, &slot);
     if (rc) return rc;
@@ -903,6 +909,378 @@ int batch_impl(smre_ctx* c, smre_dtype dt, int n, const smre_batch_image* im,
   }
   return all_conv ? SMRE_OK : SMRE_NOT_CONVERGED;
 }
+
+// ---------------------------------------------------------------- serving
+// HIP backend of the continuous-batching server (scheduler: serve_core.hpp).
+// One device arena holds every admitted request's image, snapshot, region
+// table and increments; descriptors and control blocks sit in fixed slot
+// tables, so a single captured graph (snapshot, four persistent colour
+// launches over the current work lists, delta, decide) serves every sweep
+// whatever the mix.  Requests join between sweeps; a finished request is
+// retired one sweep after its flag is set (its items are skipped meanwhile).
+class Arena {
+ public:
+  void reset(size_t total) {
+    free_.clear();
+    free_[0] = total;
+  }
+  bool alloc(size_t n, size_t* off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it)
+      if (it->second >= n) {
+        *off = it->first;
+        const size_t rest = it->second - n, at = it->first + n;
+        free_.erase(it);
+        if (rest) free_[at] = rest;
+        return true;
+      }
+    return false;
+  }
+  void release(size_t off, size_t n) {
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+
+ private:
+  std::map<size_t, size_t> free_;
+};
+
+class HipBackend : public smre_serve::Backend {
+ public:
+  explicit HipBackend(const smre_serve_config& c) : cfg_(c) {}
+  ~HipBackend() override {
+    (void)hipSetDevice(cfg_.device);
+    if (stream_) (void)hipStreamSynchronize(stream_);
+    if (gx_) (void)hipGraphExecDestroy(gx_);
+    if (graph_) (void)hipGraphDestroy(graph_);
+    if (arena_) (void)hipFree(arena_);
+    if (tables_) (void)hipFree(tables_);
+    if (hctl_) (void)hipHostFree(hctl_);
+    if (hitems_) (void)hipHostFree(hitems_);
+    for (auto& e : ev_)
+      if (e) (void)hipEventDestroy(e);
+    if (stream_) (void)hipStreamDestroy(stream_);
+  }
+
+  int init() {
+    HIP_OK(hipSetDevice(cfg_.device));
+    HIP_OK(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking));
+    size_t fr = 0, tot = 0;
+    HIP_OK(hipMemGetInfo(&fr, &tot));
+    size_t budget = cfg_.hbm_budget_bytes ? cfg_.hbm_budget_bytes : (size_t)(fr * 0.8);
+    n_ = std::max(1, cfg_.max_active);
+    const size_t tbl = align_up(sizeof(ImageDesc) * n_, 256) + align_up(sizeof(BatchCtl) * n_, 256) +
+                       4 * align_up(sizeof(WorkItem) * kCapItems, 256) + 256 +
+                       align_up(sizeof(Ctrl), 256);
+    if (budget <= tbl + (1 << 20)) return SMRE_EINVAL;
+    budget -= tbl;
+    if (hipMalloc(&arena_, budget) != hipSuccess) {
+      (void)hipGetLastError();
+      return SMRE_ENOMEM;
+    }
+    arena_size_ = budget;
+    free_.reset(budget);
+    HIP_OK(hipMalloc(&tables_, tbl));
+    unsigned char* t = (unsigned char*)tables_;
+    desc_ = (ImageDesc*)t;
+    t += align_up(sizeof(ImageDesc) * n_, 256);
+    ctl_ = (BatchCtl*)t;
+    t += align_up(sizeof(BatchCtl) * n_, 256);
+    for (int c = 0; c < 4; ++c) {
+      items_[c] = (WorkItem*)t;
+      t += align_up(sizeof(WorkItem) * kCapItems, 256);
+    }
+    cnt_ = (int*)t;
+    t += 256;
+    vctrl_ = (Ctrl*)t;
+    HIP_OK(hipHostMalloc(&hctl_, sizeof(BatchCtl) * n_ * 2, hipHostMallocDefault));
+    HIP_OK(hipHostMalloc(&hitems_, sizeof(WorkItem) * kCapItems * 4 + 64, hipHostMallocDefault));
+    for (auto& e : ev_) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    // every slot starts retired
+    std::vector<BatchCtl> c0(n_);
+    for (auto& c : c0) {
+      std::memset(&c, 0, sizeof c);
+      c.done = 1;
+      c.check_every = 1;
+    }
+    HIP_OK(hipMemcpy(ctl_, c0.data(), sizeof(BatchCtl) * n_, hipMemcpyHostToDevice));
+    HIP_OK(hipMemset(cnt_, 0, 64));
+    slot_.assign(n_, Slot());
+    int occ = 0;
+    if (cfg_.inc == SMRE_INC_BF16)
+      HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &occ, (const void*)region_phase_batch<float, bf16_t, 16, 17, true>, 128, 0));
+    else
+      HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &occ, (const void*)region_phase_batch<float, float, 16, 17, true>, 128, 0));
+    hipDeviceProp_t prop;
+    HIP_OK(hipGetDeviceProperties(&prop, cfg_.device));
+    BatchDev D;
+    D.desc = desc_;
+    D.ctl = ctl_;
+    for (int c = 0; c < 4; ++c) {
+      D.items[c] = items_[c];
+      D.grid[c] = std::max(1, occ) * prop.multiProcessorCount;
+    }
+    D.cnt = cnt_;
+    D.q = (unsigned char*)arena_;
+    D.prev = arena_;  // per-image snapshots are addressed through prev_off
+    D.n = n_;
+    D.maxh = 1024;
+    smre_batch_params bp{};
+    bp.region = 16;
+    bp.inc = cfg_.inc;
+    bp.kahan = cfg_.kahan;
+    bp.check_every = 1;
+    bp.guard_rel = cfg_.guard_rel;
+    HIP_OK(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_batch_sweep<float>(SMRE_F32, &bp, 16, D, true, stream_);
+    HIP_OK(hipStreamEndCapture(stream_, &graph_));
+    if (rc) return rc;
+    HIP_OK(hipGraphInstantiate(&gx_, graph_, nullptr, nullptr, 0));
+    return SMRE_OK;
+  }
+
+  int slots() const override { return n_; }
+  size_t budget() const override { return arena_size_; }
+
+  size_t footprint(const smre_serve::Request& r) const override {
+    Plan pl;
+    smre_params p = params_of(r);
+    if (plan_project(SMRE_F32, r.H, r.W, &p, &pl, false)) return 0;
+    return layout(pl, r, nullptr);
+  }
+
+  int admit(smre_serve::Request& r, int s) override {
+    Slot& sl = slot_[s];
+    smre_params p = params_of(r);
+    sl.plan = Plan();
+    int rc = plan_project(SMRE_F32, r.H, r.W, &p, &sl.plan, true);
+    if (rc) return rc;
+    size_t off_roff, off_x, off_prev;
+    size_t offs[3];
+    const size_t need = layout(sl.plan, r, offs);
+    off_roff = offs[0];
+    off_x = offs[1];
+    off_prev = offs[2];
+    size_t at = 0;
+    if (!free_.alloc(need, &at)) return SMRE_ENOMEM;
+    sl.off = at;
+    sl.size = need;
+    unsigned char* base = (unsigned char*)arena_ + at;
+    HIP_OK(hipSetDevice(cfg_.device));
+    HIP_OK(hipMemcpyAsync(base + off_x, r.in.data(), r.in.size() * sizeof(float),
+                          hipMemcpyHostToDevice, stream_));
+    HIP_OK(hipMemcpyAsync(base + off_roff, sl.plan.roff.data(), sl.plan.roff.size() * 8,
+                          hipMemcpyHostToDevice, stream_));
+    const int64_t nwords = (int64_t)(sl.plan.qbytes / 4);
+    hipLaunchKernelGGL((fill_kernel<uint32_t>), dim3(grid_for(nwords)), dim3(256), 0, stream_,
+                       (uint32_t*)base, nwords, 0u);
+    HIP_OK(hipGetLastError());
+    ImageDesc& a = sl.desc;
+    std::memset(&a, 0, sizeof a);
+    a.x = base + off_x;
+    a.roff = (const int64_t*)(base + off_roff);
+    a.ld = r.W;
+    a.q_byte = (int64_t)at;
+    a.H = r.H;
+    a.W = r.W;
+    a.nrx = sl.plan.nrx;
+    a.nry = sl.plan.nry;
+    a.fr = sl.plan.R + sl.plan.smax - 1;
+    a.nsides = sl.plan.nsides;
+    a.guard = (float)cfg_.guard_rel;
+    for (int k = 0; k < sl.plan.nsides; ++k) {
+      a.sides[k] = sl.plan.sides[k];
+      a.r2f[k] = (float)sl.plan.r2[k];
+      a.rf[k] = (float)std::sqrt(sl.plan.r2[k]);
+      a.r2d[k] = sl.plan.r2[k];
+    }
+    BatchCtl& c = sl.ctl;
+    std::memset(&c, 0, sizeof c);
+    c.max_sweeps = r.max_sweeps;
+    c.check_every = std::max(1, cfg_.check_every);
+    c.tol = r.tol;
+    c.last_delta = -1.0;
+    c.prev_off = (int64_t)((at + off_prev) / sizeof(float));
+    c.gen = ++generation_;
+    HIP_OK(hipMemcpyAsync(desc_ + s, &sl.desc, sizeof(ImageDesc), hipMemcpyHostToDevice, stream_));
+    HIP_OK(hipMemcpyAsync(ctl_ + s, &sl.ctl, sizeof(BatchCtl), hipMemcpyHostToDevice, stream_));
+    HIP_OK(hipStreamSynchronize(stream_));  // host staging (r.in, plan, desc) released safely
+    sl.active = true;
+    sl.reported = false;
+    sl.t_admit = smre_serve::now_s();
+    dirty_ = true;
+    return SMRE_OK;
+  }
+
+  int step(std::vector<int>& fin) override {
+    HIP_OK(hipSetDevice(cfg_.device));
+    if (dirty_) {
+      int rc = upload_lists();
+      if (rc) return rc;
+    }
+    HIP_OK(hipGraphLaunch(gx_, stream_));
+    const int k = parity_;
+    HIP_OK(hipMemcpyAsync(hctl_ + k * n_, ctl_, sizeof(BatchCtl) * n_, hipMemcpyDeviceToHost,
+                          stream_));
+    HIP_OK(hipEventRecord(ev_[k], stream_));
+    parity_ ^= 1;
+    // read the control blocks of the previous sweep (one sweep of lag)
+    const int pk = parity_;
+    if (have_prev_) {
+      HIP_OK(hipEventSynchronize(ev_[pk]));
+      for (int i = 0; i < n_; ++i) {
+        Slot& sl = slot_[i];
+        if (sl.active && !sl.reported && sl.finished_in(hctl_[pk * n_ + i])) {
+          sl.last = hctl_[pk * n_ + i];
+          sl.reported = true;
+          fin.push_back(i);
+        }
+      }
+    }
+    have_prev_ = true;
+    return SMRE_OK;
+  }
+
+  int retire(smre_serve::Request& r, int s) override {
+    Slot& sl = slot_[s];
+    HIP_OK(hipSetDevice(cfg_.device));
+    // the sweep in flight skips this image (done flag), so x is final
+    r.out.resize((size_t)r.H * r.W);
+    HIP_OK(hipMemcpyAsync(r.out.data(), sl.desc.x, r.out.size() * sizeof(float),
+                          hipMemcpyDeviceToHost, stream_));
+    HIP_OK(hipStreamSynchronize(stream_));
+    std::memset(&r.rep, 0, sizeof r.rep);
+    r.rep.sweeps = sl.last.done_sweep;
+    r.rep.converged = sl.last.converged;
+    r.rep.region = 16;
+    r.rep.last_delta = sl.last.last_delta;
+    double worst = 0.0;
+    hipLaunchKernelGGL(ctrl_reset_kernel, dim3(1), dim3(1), 0, stream_, vctrl_);
+    for (int k = 0; k < sl.plan.nsides; ++k) {
+      const int64_t nw = (int64_t)(r.H - sl.plan.sides[k] + 1) * (r.W - sl.plan.sides[k] + 1);
+      hipLaunchKernelGGL((violation_kernel<float>), dim3(grid_for(nw)), dim3(256), 0, stream_,
+                         (const float*)sl.desc.x, (int64_t)r.W, r.H, r.W, sl.plan.sides[k],
+                         sl.plan.r2[k], vctrl_);
+    }
+    HIP_OK(hipGetLastError());
+    Ctrl vc;
+    HIP_OK(hipMemcpyAsync(&vc, vctrl_, sizeof(Ctrl), hipMemcpyDeviceToHost, stream_));
+    HIP_OK(hipStreamSynchronize(stream_));
+    worst = dkey_inv(vc.viol_key);
+    r.rep.max_violation = worst;
+    r.rep.elapsed_ms = (smre_serve::now_s() - sl.t_admit) * 1e3;
+    r.rep.bytes_moved = (double)sl.last.done_sweep *
+                        (2.0 * (cfg_.inc == SMRE_INC_BF16 ? 2 : 4) * (double)sl.plan.nq +
+                         8.0 * (double)r.H * r.W);
+    r.rep.window_projections = (double)sl.last.done_sweep * (double)sl.plan.nwin;
+    free_.release(sl.off, sl.size);
+    sl.active = false;
+    dirty_ = true;
+    return SMRE_OK;
+  }
+
+ private:
+  static constexpr int kCapItems = 1 << 18;
+  struct Slot {
+    bool active = false, reported = false;
+    size_t off = 0, size = 0;
+    Plan plan;
+    ImageDesc desc;
+    BatchCtl ctl;
+    BatchCtl last;
+    double t_admit = 0;
+    // a control-block copy belongs to this occupant and says it has finished
+    bool finished_in(const BatchCtl& c) const { return c.done && c.gen == ctl.gen; }
+  };
+
+  smre_params params_of(const smre_serve::Request& r) const {
+    smre_params p{};
+    p.n_sides = (int)r.sides.size();
+    p.sides = r.sides.data();
+    p.radius2 = r.r2.data();
+    p.tol = r.tol;
+    p.max_sweeps = r.max_sweeps;
+    p.check_every = std::max(1, cfg_.check_every);
+    p.region = 16;
+    p.inc = cfg_.inc;
+    p.kahan = cfg_.kahan;
+    p.guard_rel = cfg_.guard_rel;
+    return p;
+  }
+
+  // bytes of one request's block: increments (+ slack), region table, image, snapshot
+  size_t layout(const Plan& pl, const smre_serve::Request& r, size_t* offs) const {
+    size_t o = align_up(pl.qbytes, 256);
+    if (offs) offs[0] = o;
+    o = align_up(o + ((size_t)pl.nry * pl.nrx + 1) * 8, 256);
+    if (offs) offs[1] = o;
+    o = align_up(o + (size_t)r.H * r.W * 4, 256);
+    if (offs) offs[2] = o;
+    o = align_up(o + (size_t)r.H * r.W * 4, 256);
+    return o;
+  }
+
+  int upload_lists() {
+    // the previous upload's staging must be consumed before it is rewritten
+    HIP_OK(hipStreamSynchronize(stream_));
+    int cnt[6] = {0, 0, 0, 0, 0, 0};
+    WorkItem* h = hitems_;
+    for (int i = 0; i < n_; ++i) {
+      const Slot& sl = slot_[i];
+      if (!sl.active || sl.reported) continue;
+      for (int ry = 0; ry < sl.plan.nry; ++ry)
+        for (int rx = 0; rx < sl.plan.nrx; ++rx) {
+          const int c = (ry & 1) * 2 + (rx & 1);
+          if (cnt[c] >= kCapItems) return SMRE_ENOMEM;
+          h[c * kCapItems + cnt[c]++] = WorkItem{i, ry * sl.plan.nrx + rx};
+        }
+    }
+    for (int c = 0; c < 4; ++c)
+      if (cnt[c])
+        HIP_OK(hipMemcpyAsync(items_[c], h + c * kCapItems, sizeof(WorkItem) * cnt[c],
+                              hipMemcpyHostToDevice, stream_));
+    std::memcpy(hitems_ + 4 * kCapItems, cnt, 4 * sizeof(int));
+    HIP_OK(hipMemcpyAsync(cnt_, hitems_ + 4 * kCapItems, 4 * sizeof(int), hipMemcpyHostToDevice,
+                          stream_));
+    dirty_ = false;
+    return SMRE_OK;
+  }
+
+  smre_serve_config cfg_;
+  int n_ = 0;
+  hipStream_t stream_ = nullptr;
+  void* arena_ = nullptr;
+  size_t arena_size_ = 0;
+  Arena free_;
+  void* tables_ = nullptr;
+  ImageDesc* desc_ = nullptr;
+  BatchCtl* ctl_ = nullptr;
+  WorkItem* items_[4] = {};
+  int* cnt_ = nullptr;
+  Ctrl* vctrl_ = nullptr;  // feasibility check of a retiring request
+  BatchCtl* hctl_ = nullptr;
+  WorkItem* hitems_ = nullptr;
+  hipEvent_t ev_[2] = {};
+  int parity_ = 0;
+  bool have_prev_ = false;
+  bool dirty_ = false;
+  int generation_ = 0;
+  hipGraph_t graph_ = nullptr;
+  hipGraphExec_t gx_ = nullptr;
+  std::vector<Slot> slot_;
+};
 
 // ---------------------------------------------------------------- bounds
 // Regularised lower incomplete gamma P(a, x): power series for x < a + 1,
@@ -1164,4 +1542,53 @@ int smre_max_violation(smre_ctx* c, smre_dtype dt, const void* x, int64_t H, int
   return SMRE_EINVAL;
 }
 
+struct smre_server {
+  std::unique_ptr<smre_serve::Server> srv;
+};
+
+int smre_serve_create(const smre_serve_config* cfg, smre_server** out) {
+  if (!cfg || !out) return SMRE_EINVAL;
+  if (cfg->max_active < 1 || cfg->queue_cap < 1) return SMRE_EINVAL;
+  if (cfg->inc != SMRE_INC_SAME && cfg->inc != SMRE_INC_BF16) return SMRE_EINVAL;
+  int n = 0;
+  HIP_OK(hipGetDeviceCount(&n));
+  if (cfg->device < 0 || cfg->device >= n) return SMRE_EINVAL;
+  auto be = std::make_unique<HipBackend>(*cfg);
+  const int rc = be->init();
+  if (rc) return rc;
+  smre_server* s = new smre_server();
+  s->srv = std::make_unique<smre_serve::Server>(std::move(be), cfg->queue_cap);
+  *out = s;
+  return SMRE_OK;
+}
+
+void smre_serve_destroy(smre_server* s) { delete s; }
+
+int smre_serve_submit(smre_server* s, const float* x, int32_t H, int32_t W, const smre_params* p,
+                      uint64_t* ticket) {
+  if (!s) return SMRE_EINVAL;
+  return s->srv->submit(x, H, W, p, ticket);
+}
+
+int smre_serve_poll(smre_server* s, uint64_t ticket, float* out, size_t out_elems,
+                    smre_report* rep, double* latency_s) {
+  if (!s) return SMRE_EINVAL;
+  return s->srv->poll(ticket, out, out_elems, rep, latency_s);
+}
+
+int smre_serve_stats(smre_server* s, smre_serve_counters* out) {
+  if (!s || !out) return SMRE_EINVAL;
+  const smre_serve::Stats st = s->srv->stats();
+  out->submitted = st.submitted;
+  out->completed = st.completed;
+  out->rejected = st.rejected;
+  out->failed = st.failed;
+  out->active = st.active;
+  out->queued = st.queued;
+  out->sweeps = st.sweeps;
+  out->bytes_in_use = (int64_t)st.bytes_in_use;
+  return SMRE_OK;
+}
+
 }  // extern "C"
+
