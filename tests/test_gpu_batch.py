@@ -123,3 +123,17 @@ def test_batch_uneven_full_size_sample(ctx):
         y = dev(x0s[k], torch.float32)
         ctx.project(y, sides, r2, tol=0, max_sweeps=3, region=16)
         assert torch.equal(xs[k], y)
+
+
+@pytest.mark.parametrize("grid", [1, 3])
+def test_batch_few_workgroups_walk_many_items(ctx, grid):
+    """A persistent workgroup processes several regions in sequence."""
+    sides = list(range(1, 9))
+    r2 = oracle.chi2_bounds(sides)
+    x0s = images()
+    xs = [dev(x, torch.float64) for x in x0s]
+    ctx.project_batch(xs, sides, r2, tol=0, max_sweeps=2, region=16, grid=grid)
+    for x0, x in zip(x0s, xs):
+        ref, _, _ = oracle.dykstra(x0, sides, r2, tol=0, max_sweeps=2,
+                                   order=oracle.ORDER_REGION, region=16)
+        assert np.max(np.abs(x.cpu().numpy() - ref)) <= 1e-12 * np.max(np.abs(ref))
