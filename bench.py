@@ -25,13 +25,52 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1503_03492_amd", "csrc", "kernels.hpp")
+
+
+def measured_traffic(profile):
+    """HBM bytes per launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE, calibrated against a 1 GiB copy), or None when the kernel
+    source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", profile)
+    if not os.path.exists(path):
+        return None
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", "`", "#")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    src = [v for k, v in fields.items() if k.startswith("kernel_source_sha256")]
+    if not src or src[0] != sha or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
+def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=5):
+    """Read + write GB/s of a plain 1 GiB device-to-device copy: the practical
+    ceiling a streaming kernel is compared with beside the 8 TB/s peak."""
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
 def workload(name):
     if name == "c3":
         return dict(workload="dykstra_1024sq_sides1-16_fp32", H=1024, W=1024, n_e=2000,
                     sides=list(range(1, 17)), dtype="fp32", tol=1e-5, max_sweeps=5000,
-                    inc="f32")
+                    inc="f32", profile="region_phase_1024sq_sides1-16_fp32.md")
     if name == "c3bf16":
         return dict(workload="dykstra_1024sq_sides1-16_fp32_bf16inc", H=1024, W=1024, n_e=2000,
                     sides=list(range(1, 17)), dtype="fp32", tol=1e-5, max_sweeps=5000,
@@ -211,6 +250,7 @@ def bench_icd(args):
         reps.append(ctx.incomplete(x, K, r2, tol=1e-3, mode=smre.TOL_MEANABS, max_inner=10000))
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    copy_gbs = copy_bandwidth(torch, dev)
     wp = sum(r["window_projections"] for r in reps)
     kms = sum(r["kernel_ms"] for r in reps)
     by = sum(r["bytes_moved"] for r in reps)
@@ -291,6 +331,9 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--max-active", type=int, default=16)
     ap.add_argument("--serve-baseline", action="store_true")
+    ap.add_argument("--profile-sweeps", type=int, default=0,
+                    help="counter-collection mode: one 1 GiB device copy (the calibration "
+                         "kernel), then this many sweeps of the workload; no timing line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the projection of one image does not shard "
@@ -329,6 +372,25 @@ def main():
         rc, rep = ctx.project(x, sides, r2, opts)
         return rc, rep
 
+    if args.profile_sweeps > 0:
+        # Under rocprofv3 --pmc: the copy reads and writes exactly 1 GiB, which
+        # scales FETCH_SIZE / WRITE_SIZE; then a few sweeps of the workload.
+        a = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        x.copy_(x0_dev)
+        prof = smre.ProjectOptions(tol=0.0, max_sweeps=args.profile_sweeps, check_every=1,
+                                   region=args.region, kahan=True, guard_rel=1e-5, inc=opts.inc)
+        rc, rep = ctx.project(x, sides, r2, prof)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_sweeps": rep["sweeps"], "kernel_launches":
+                          rep["kernel_launches"], "bytes_per_launch":
+                          rep["bytes_moved"] / max(1, rep["kernel_launches"]),
+                          "kernel_ms": rep["kernel_ms"]}), flush=True)
+        return
+
     for i in range(args.warmup):
         rc, rep = step()
         print(f"warmup {i}: {rep['sweeps']} sweeps, {rep['elapsed_ms']:.1f} ms", file=sys.stderr,
@@ -344,6 +406,7 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
 
+    copy_gbs = copy_bandwidth(torch, dev)
     wp = sum(r["window_projections"] for r in reps)
     sweeps = [r["sweeps"] for r in reps]
     kms = sum(r["kernel_ms"] for r in reps)
@@ -371,8 +434,12 @@ def main():
         "max_violation": max(r["max_violation"] for r in reps),
         "sweep_kernel_avg_us": kms / launches * 1e3 if launches else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS if achieved else None,
+                     "traffic": measured_traffic(wl["profile"]) if "profile" in wl and
+                     args.region in (0, 16) else None,
                      "kernel": "region_phase",
+                     "copy_gbs_measured": copy_gbs,
+                     "frac_of_copy": achieved / copy_gbs if achieved and copy_gbs else None,
                      "bytes_per_launch": bytes_alg / launches if launches else None},
     }
     if not args.no_cpu_baseline:
