@@ -14,24 +14,30 @@
 //   wave 0 (consumer) keeps the region's x footprint in LDS for the whole
 //     phase and runs the steps: y = x + I, n = sum y^2 per window (lanes of a
 //     window reduce with DPP / permlane swaps), t = sqrt(r2/n) if n > r2,
-//     x' = t y, I' = y - x'.  I' goes straight to HBM.
-//   wave 1 (producer) streams the region's increments -- one contiguous byte
-//     range of the increment buffer per region and sweep -- through a ring of
-//     1 KiB pages in LDS, several loads in flight, gated by the consumer's
-//     progress.  The first pages of the ring are mirrored after its end so a
-//     round's chunk is always a linear LDS range.  The two waves synchronise
-//     through two LDS counters only.
+//     x' = t y, I' = y - x'.  I' is written back into the ring in place.
+//   wave 1 (producer) streams the region's increments -- one page-aligned
+//     contiguous byte range of the increment buffer per region and sweep --
+//     through a ring of 1 KiB pages in LDS, several loads in flight, and
+//     writes every page the consumer has finished back to HBM with 16-byte
+//     stores before its slot is reused.  The first pages of the ring are
+//     mirrored after its end so a round's chunk is always a linear LDS range
+//     to read; a round that runs into the mirror copies its updated bytes back
+//     to the primary pages.  The two waves synchronise through LDS counters;
+//     every wait is bounded and sets an abort flag when the bound is hit, so
+//     the workgroup always drains.
 //
-// With one consumer wave per SIMD every instruction costs an issue slot, so
-// the step is written for instruction count: a lane serves a fixed window
-// slot per side, so its LDS pixel addresses are one base plus compile-time
-// immediates; increments are laid out window-major inside a round so the
-// per-slot offsets are immediates too; stores of masked lanes are dropped by
-// the buffer unit (out-of-range offset) instead of branching.
+// With one consumer wave per SIMD the step is latency- and issue-bound, so it
+// is written for short dependency chains and few instructions: no vector
+// memory operations in the consumer, scalar-only progress checks, a lane
+// serves a fixed window slot per side (its LDS pixel and ring addresses are
+// one base plus compile-time immediates), masked lanes write to a dummy LDS
+// area instead of branching, and the FP64 guard-band recheck branches after
+// the writes it may redo.
 //
-// Increment layout: per region (raster order), its steps in visiting order;
-// per step, rounds of up to BR x BC windows; per round, the valid windows in
-// row-major order, S^2 elements each, ordered by slot (u, v) then lane.
+// Increment layout: per region (raster order, each region starting on a page
+// boundary), its steps in visiting order; per step, rounds of up to BR x BC
+// windows; per round, the valid windows in row-major order, S^2 elements each,
+// ordered by slot (u, v) then lane.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -54,36 +60,23 @@ __device__ __forceinline__ bf16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
-// Increment element I/O: read from the LDS ring, write to HBM through a raw
-// buffer resource.  A store whose byte offset lies past the resource's
-// num_records is dropped by the hardware, which masks lanes without branches.
-constexpr uint32_t kDropOffset = 0x80000000u;
-constexpr int kRsrcWord3 = 0x00020000;
+constexpr int kSpinLimit = 1 << 20;   // sleeps before a wait gives up (~30 ms)
 
+// Increment element I/O in the LDS ring (BF16 storage rounds to nearest even).
 template <typename TQ, typename TC> struct QStore;
 template <> struct QStore<float, float> {
   static __device__ __forceinline__ float get(const unsigned char* p) { return *(const float*)p; }
-  static __device__ __forceinline__ void put(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
-                                             float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
-  }
+  static __device__ __forceinline__ void put(unsigned char* p, float v) { *(float*)p = v; }
 };
 template <> struct QStore<double, double> {
   static __device__ __forceinline__ double get(const unsigned char* p) { return *(const double*)p; }
-  static __device__ __forceinline__ void put(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
-                                             double v) {
-    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
-  }
+  static __device__ __forceinline__ void put(unsigned char* p, double v) { *(double*)p = v; }
 };
 template <> struct QStore<bf16_t, float> {
   static __device__ __forceinline__ float get(const unsigned char* p) {
     return bf2f(*(const bf16_t*)p);
   }
-  static __device__ __forceinline__ void put(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
-                                             float v) {
-    __builtin_amdgcn_raw_buffer_store_b16(f2bf(v), r, voff, soff, 0);
-  }
+  static __device__ __forceinline__ void put(unsigned char* p, float v) { *(bf16_t*)p = f2bf(v); }
 };
 
 // ---------------------------------------------------------------- lane patterns
@@ -184,7 +177,21 @@ template <typename TX, typename TQ, int R, int SMAX> struct PhaseShape {
     return (m * (int)sizeof(TQ) + kPage - 1) / kPage + 1;
   }
   static constexpr int MIRROR = mirror();
-  static constexpr int RING = (kSlots + MIRROR) * kPage;
+  // dummy area for the increment writes of masked lanes: largest slot
+  // immediate + one element
+  static constexpr int qdummy() {
+    int m = 0;
+    for (int s = 1; s <= SMAX; ++s) {
+      const Pattern p = pattern(R, s);
+      const int U = (s + p.gr - 1) / p.gr, V = (s + p.gc - 1) / p.gc;
+      const int jrl = s - (U - 1) * p.gr;
+      const int d = ((U - 1) * p.gr * s + jrl * (V - 1) * p.gc + 1) * (int)sizeof(TQ);
+      if (d > m) m = d;
+    }
+    return (m + 15) / 16 * 16;
+  }
+  static constexpr int QD = (kSlots + MIRROR) * kPage;  // ring byte offset of the dummy area
+  static constexpr int RING = QD + qdummy();
   static_assert(MIRROR + 2 <= kSlots, "ring too small for a round");
 };
 
@@ -314,14 +321,28 @@ struct WorkItem {
   int32_t region;
 };
 
+// Bounded wait until *ctr >= target; returns the last value read (SGPR).
+// When the bound is hit, or the other wave has given up, the abort flag is set
+// and the wait returns, so every wave of the workgroup finishes.
+__device__ __forceinline__ int wait_ge(const int* ctr, int target, int* abort) {
+  int seen = __builtin_amdgcn_readfirstlane(lds_load(ctr));
+  for (int spin = 0; seen < target; ++spin) {
+    if (spin >= kSpinLimit || lds_load(abort)) {
+      lds_store(abort, 1);
+      return target;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    seen = __builtin_amdgcn_readfirstlane(lds_load(ctr));
+  }
+  return seen;
+}
+
 struct Consumer {
-  const unsigned char* ring;
+  unsigned char* ring;
   int* ready;      // pages (relative to the region's first page) present in the ring
-  int* consumed;   // first page (relative) still needed
-  __amdgpu_buffer_rsrc_t rsrc;  // the region's increments
+  int* consumed;   // pages (relative) whose updated increments are all in the ring
+  int* abort;      // set by a wait that gave up
   uint32_t qb;     // next increment byte of the region (relative)
-  uint32_t pb0;    // byte offset of the region start inside its first page
-  uint32_t rb0;    // ring byte offset of the region start
   int r0, c0;      // anchor origin of the region (= footprint origin)
   int lane;
   int ready_seen;  // last value read from *ready
@@ -345,9 +366,11 @@ __device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs
   const int lane_x0 = (S * bry + jr) * P + (S * brx + jc);
   const int rhi = min(R, a.H - S + 1 - c.r0), chi = min(R, a.W - S + 1 - c.c0);
   if (rhi <= 0 || chi <= 0) return;
-  const TX r2 = (sizeof(TX) == 8) ? (TX)a.r2d[k] : (TX)a.r2f[k];
-  const float rfl = a.rf[k];
+  // per-side constants live in VGPRs (the loop would otherwise reload them)
+  TX r2 = (sizeof(TX) == 8) ? (TX)a.r2d[k] : (TX)a.r2f[k];
+  float rfl = a.rf[k], gr2 = a.guard * a.r2f[k];
   const double r2d = a.r2d[k];
+  __asm__ volatile("" : "+v"(r2), "+v"(rfl), "+v"(gr2));
 
   for (int ap = 0; ap < S; ++ap) {
     const int nr = (rhi - ap + S - 1) / S;
@@ -363,21 +386,21 @@ __device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs
           const bool valid = bry < nbr && brx < nbc;
           const int woff = (bry * nbc + brx) * (S * S);
           const uint32_t rb = c.qb;
-          c.qb += (uint32_t)(nwr * S * S * ES);
+          const uint32_t nbytes = (uint32_t)(nwr * S * S * ES);
+          c.qb += nbytes;
           // wait until every page holding this round's bytes is in the ring
-          const int need = (int)((c.pb0 + c.qb + kPage - 1) / kPage);
-          if (need > c.ready_seen) {
-            while ((c.ready_seen = lds_load(c.ready)) < need) __builtin_amdgcn_s_sleep(1);
-          }
+          const int need = (int)((c.qb + kPage - 1) / kPage);
+          if (need > c.ready_seen) c.ready_seen = wait_ge(c.ready, need, c.abort);
           __asm__ volatile("" ::: "memory");
-          const uint32_t roff = (c.rb0 + rb) & RMASK;
-          // ring addresses (full / last column slots) and masked store offsets
-          const unsigned char* qrf = c.ring + roff + (woff + ef) * ES;
-          const unsigned char* qrl = c.ring + roff + (woff + el) * ES;
-          const uint32_t sff = valid ? (uint32_t)((woff + ef) * ES) : kDropOffset;
-          const uint32_t sfl = valid && cl ? (uint32_t)((woff + el) * ES) : kDropOffset;
-          const uint32_t slf = valid && rl ? (uint32_t)((woff + ef) * ES) : kDropOffset;
-          const uint32_t sll = valid && rl && cl ? (uint32_t)((woff + el) * ES) : kDropOffset;
+          const uint32_t roff = rb & RMASK;
+          // ring offsets of the lane's elements (full / last column slot); the
+          // writes of masked lanes go to the dummy area
+          const uint32_t qf = roff + (uint32_t)((woff + ef) * ES);
+          const uint32_t ql = roff + (uint32_t)((woff + el) * ES);
+          const uint32_t wff = valid ? qf : (uint32_t)LS::QD;
+          const uint32_t wfl = valid && cl ? ql : (uint32_t)LS::QD;
+          const uint32_t wlf = valid && rl ? qf : (uint32_t)LS::QD;
+          const uint32_t wll = valid && rl && cl ? ql : (uint32_t)LS::QD;
           const int bx = lane_x0 + (ap + S * rby) * P + (bp + S * rbx);
           const int bxr = valid ? bx : 0;
           const int bxw = valid ? bx : LS::XDUMMY;
@@ -391,7 +414,7 @@ __device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs
           for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-              qv[u][v] = QS::get((v == V - 1 ? qrl : qrf) + SS::slot(u, v) * ES);
+              qv[u][v] = QS::get(c.ring + (v == V - 1 ? ql : qf) + SS::slot(u, v) * ES);
               xv[u][v] = xs[bxr + u * GR * P + v * GC];
             }
           // 2) y = x + I (pixels outside the window count as 0), sum of squares
@@ -421,12 +444,31 @@ __device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs
             }
           if constexpr (sizeof(TX) == 4 && KAHAN) acc -= comp;
           const TX n = group_sum<G>(acc);
-          TX t;
+
+          // 3) x' = t y into the footprint, I' = y - x' into the ring
+          auto write_step = [&](TX t) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+              for (int v = 0; v < V; ++v) {
+                const bool part_r = (u == U - 1) && (JRL < GR);
+                const bool part_c = (v == V - 1) && (JCL < GC);
+                const int base = (part_r && part_c) ? bxw_rc : part_r ? bxw_r : part_c ? bxw_c : bxw;
+                const uint32_t wq = (u == U - 1 && JRL < GR) ? ((v == V - 1) ? wll : wlf)
+                                                            : ((v == V - 1) ? wfl : wff);
+                const TX xn = t * y[u][v];
+                xs[base + u * GR * P + v * GC] = xn;
+                QS::put(c.ring + wq + SS::slot(u, v) * ES, y[u][v] - xn);
+              }
+          };
           if constexpr (sizeof(TX) == 4) {
-            t = n > r2 ? rfl * __builtin_amdgcn_rsqf(n) : 1.0f;
-            // FP64 recheck of windows whose sum lies within the guard band.
-            const bool near = fabsf(n - r2) <= a.guard * r2;
-            if (__any(near)) {
+            // FP32 scale; windows whose sum lies within the guard band of the
+            // bound are redone with an FP64 sum after the writes
+            const bool near = fabsf(n - r2) <= gr2;
+            uint64_t nearmask = __ballot(near);
+            __asm__ volatile("" : "+s"(nearmask) :: "memory");
+            write_step(n > r2 ? rfl * __builtin_amdgcn_rsqf(n) : 1.0f);
+            if (nearmask) {
               double pd = 0.0;
 #pragma unroll
               for (int u = 0; u < U; ++u)
@@ -434,26 +476,20 @@ __device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs
                 for (int v = 0; v < V; ++v)
                   pd = __builtin_fma((double)y[u][v], (double)y[u][v], pd);
               const double nd = group_sum<G>(pd);
-              if (near) t = nd > r2d ? (float)__builtin_sqrt(r2d / nd) : 1.0f;
+              const float t64 = nd > r2d ? (float)__builtin_sqrt(r2d / nd) : 1.0f;
+              write_step(near ? t64 : (n > r2 ? rfl * __builtin_amdgcn_rsqf(n) : 1.0f));
             }
           } else {
-            t = n > r2 ? __builtin_sqrt(r2 / n) : TX(1);
+            write_step(n > r2 ? __builtin_sqrt(r2 / n) : TX(1));
           }
-          // 3) x' = t y into the footprint, I' = y - x' to HBM
-#pragma unroll
-          for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-              const bool part_r = (u == U - 1) && (JRL < GR);
-              const bool part_c = (v == V - 1) && (JCL < GC);
-              const int base = (part_r && part_c) ? bxw_rc : part_r ? bxw_r : part_c ? bxw_c : bxw;
-              const uint32_t so = (u == U - 1) ? ((v == V - 1) ? sll : slf) : ((v == V - 1) ? sfl : sff);
-              const TX xn = t * y[u][v];
-              xs[base + u * GR * P + v * GC] = xn;
-              QS::put(c.rsrc, so, rb + SS::slot(u, v) * ES, y[u][v] - xn);
-            }
+          // a round that ran into the mirrored pages copies them back
+          if (roff + nbytes > (uint32_t)(kSlots * kPage)) {
+            const int np = (int)((roff + nbytes - kSlots * kPage + kPage - 1) / kPage);
+            u32x4* r4 = (u32x4*)c.ring;
+            for (int p = 0; p < np; ++p) r4[p * 64 + c.lane] = r4[(kSlots + p) * 64 + c.lane];
+          }
           __asm__ volatile("" ::: "memory");
-          lds_store(c.consumed, (int)((c.pb0 + c.qb) / kPage));
+          lds_store(c.consumed, (int)(c.qb / kPage));
         }
       }
     }
@@ -480,71 +516,79 @@ __device__ __forceinline__ void dispatch_side(const ImageDesc& a, Consumer& c, T
   }
 }
 
-// Producer wave: copy pages [p_lo, p_hi) of the increment stream into the
-// ring (slot = page mod kSlots; slots below MIRROR also after the ring end),
-// kPrefetch loads in flight, never more than kSlots pages ahead of the
-// consumer.  Full batches of kPrefetch pages run branch-free so the loads stay
-// in flight across batches; the last partial batch drains.
+// Producer wave: stream pages [0, npg) of the region's increments (gq points
+// at its first page) into the ring (slot = page mod kSlots; slots below MIRROR
+// also after the ring end), kPrefetch loads in flight.  A slot is refilled
+// only after its previous page has been written back to HBM, and a page is
+// written back (one 16-byte store per lane) once the consumer has finished
+// it.  Full batches of kPrefetch pages run branch-free so the loads stay in
+// flight across batches.
 template <int MIRROR>
-__device__ __forceinline__ void put_page(u32x4* ring, int64_t page, int rel, int lane, u32x4 v,
-                                         int* ready, const int* consumed, int& cons_seen) {
-  if (rel >= cons_seen + kSlots) {
-    while (rel >= (cons_seen = lds_load(consumed)) + kSlots) __builtin_amdgcn_s_sleep(2);
-  }
-  __asm__ volatile("" ::: "memory");
-  const int slot = (int)(page & (kSlots - 1));
-  ring[slot * 64 + lane] = v;
-  if (slot < MIRROR) ring[(kSlots + slot) * 64 + lane] = v;
-  lds_store(ready, rel + 1);
-}
-
-template <int MIRROR>
-__device__ __forceinline__ void produce(const u32x4* src, int64_t p_lo, int64_t p_hi, u32x4* ring,
-                                        int* ready, const int* consumed, int lane) {
-  const int npg = (int)(p_hi - p_lo);
+__device__ __forceinline__ void produce(u32x4* gq, int npg, u32x4* ring, int* ready,
+                                        const int* consumed, int* abort, int lane) {
   if (npg <= 0) return;
-  int cons_seen = 0;
+  int cons_seen = 0, wb = 0;
+  auto writeback = [&]() {
+    if (wb >= cons_seen) cons_seen = wait_ge(consumed, wb + 1, abort);
+    __asm__ volatile("" ::: "memory");
+    const u32x4 v = ring[(wb & (kSlots - 1)) * 64 + lane];
+    __builtin_nontemporal_store(v, gq + (int64_t)wb * 64 + lane);
+    ++wb;
+  };
+  auto put = [&](int rel, u32x4 v) {
+    while (wb <= rel - kSlots) writeback();
+    __asm__ volatile("" ::: "memory");
+    const int slot = rel & (kSlots - 1);
+    ring[slot * 64 + lane] = v;
+    if (slot < MIRROR) ring[(kSlots + slot) * 64 + lane] = v;
+    lds_store(ready, rel + 1);
+  };
   u32x4 buf[kPrefetch];
 #pragma unroll
   for (int k = 0; k < kPrefetch; ++k)
-    buf[k] = __builtin_nontemporal_load(src + (p_lo + min(k, npg - 1)) * 64 + lane);
+    buf[k] = __builtin_nontemporal_load(gq + (int64_t)min(k, npg - 1) * 64 + lane);
   int base = 0;
   for (; base + kPrefetch <= npg; base += kPrefetch) {
 #pragma unroll
     for (int k = 0; k < kPrefetch; ++k) {
       const int rel = base + k;
-      put_page<MIRROR>(ring, p_lo + rel, rel, lane, buf[k], ready, consumed, cons_seen);
-      buf[k] = __builtin_nontemporal_load(src + (p_lo + min(rel + kPrefetch, npg - 1)) * 64 + lane);
+      put(rel, buf[k]);
+      buf[k] = __builtin_nontemporal_load(gq + (int64_t)min(rel + kPrefetch, npg - 1) * 64 + lane);
     }
   }
 #pragma unroll
   for (int k = 0; k < kPrefetch; ++k)
-    if (base + k < npg)
-      put_page<MIRROR>(ring, p_lo + base + k, base + k, lane, buf[k], ready, consumed, cons_seen);
+    if (base + k < npg) put(base + k, buf[k]);
+  while (wb < npg) writeback();
 }
 
 template <typename TX, typename TQ, int R, int SMAX> struct PhaseLds {
   using SH = PhaseShape<TX, TQ, R, SMAX>;
   unsigned char ring[SH::RING];
   TX xs[SH::XSIZE];
-  int ctr[2];
+  int ctr[3];  // pages ready, pages consumed, abort flag
 };
 
+// Set when a wait inside a region job gave up (a protocol failure, reported
+// as a device error by the host).
+__device__ int g_wait_abort;
+
 // One region of one image: both waves of the workgroup enter; the caller
-// synchronises the workgroup before and after.
+// resets the counters and synchronises the workgroup before and after.
 template <typename TX, typename TQ, int R, int SMAX, bool KAHAN>
 __device__ __forceinline__ void region_job(const ImageDesc& a, int region, unsigned char* q,
                                            PhaseLds<TX, TQ, R, SMAX>& L) {
   using SH = PhaseShape<TX, TQ, R, SMAX>;
   const int ry = region / a.nrx, rx = region - (region / a.nrx) * a.nrx;
+  // regions start on a page boundary of the increment stream
   const int64_t byte_lo = a.q_byte + a.roff[region] * (int64_t)sizeof(TQ);
   const int64_t byte_hi = a.q_byte + a.roff[region + 1] * (int64_t)sizeof(TQ);
-  const int64_t p_lo = byte_lo / kPage;
-  const int64_t p_hi = (byte_hi + kPage - 1) / kPage;
+  const int npg = (int)((byte_hi - byte_lo + kPage - 1) / kPage);
   const int lane = threadIdx.x & 63;
 
   if (threadIdx.x >= 64) {
-    produce<SH::MIRROR>((const u32x4*)q, p_lo, p_hi, (u32x4*)L.ring, &L.ctr[0], &L.ctr[1], lane);
+    produce<SH::MIRROR>((u32x4*)(q + byte_lo), npg, (u32x4*)L.ring, &L.ctr[0], &L.ctr[1],
+                        &L.ctr[2], lane);
     return;
   }
 
@@ -562,22 +606,36 @@ __device__ __forceinline__ void region_job(const ImageDesc& a, int region, unsig
   c.ring = L.ring;
   c.ready = &L.ctr[0];
   c.consumed = &L.ctr[1];
-  c.rsrc = __builtin_amdgcn_make_buffer_rsrc(q + byte_lo, (short)0, (int)(byte_hi - byte_lo),
-                                            kRsrcWord3);
+  c.abort = &L.ctr[2];
   c.qb = 0;
-  c.pb0 = (uint32_t)(byte_lo - p_lo * kPage);
-  c.rb0 = (uint32_t)(byte_lo & (kSlots * kPage - 1));
   c.r0 = r0;
   c.c0 = c0;
   c.lane = lane;
   c.ready_seen = 0;
   for (int k = 0; k < a.nsides; ++k) dispatch_side<TX, TQ, R, SMAX, KAHAN>(a, c, xs, k);
-
   __asm__ volatile("" ::: "memory");
+  lds_store(c.consumed, npg);  // the last, partial page too
+
   for (int idx = lane; idx < fh * fw; idx += 64) {
     const int i = idx / fw, j = idx - (idx / fw) * fw;
     xg[(int64_t)(r0 + i) * a.ld + c0 + j] = xs[i * SH::P + j];
   }
+}
+
+template <typename TX, typename TQ, int R, int SMAX>
+__device__ __forceinline__ void reset_counters(PhaseLds<TX, TQ, R, SMAX>& L) {
+  if (threadIdx.x == 0) {
+    L.ctr[0] = 0;
+    L.ctr[1] = 0;
+    L.ctr[2] = 0;
+  }
+  __syncthreads();
+}
+
+template <typename TX, typename TQ, int R, int SMAX>
+__device__ __forceinline__ void report_abort(PhaseLds<TX, TQ, R, SMAX>& L) {
+  __syncthreads();
+  if (threadIdx.x == 0 && L.ctr[2]) atomicOr(&g_wait_abort, 1);
 }
 
 // One image, one colour: block b takes the b-th region of colour (cy, cx).
@@ -588,12 +646,9 @@ __global__ __launch_bounds__(128) void region_phase(ImageDesc a, int cy, int cx,
   if (*done) return;
   const int b = blockIdx.x;
   const int region = (cy + 2 * (b / ncx)) * a.nrx + cx + 2 * (b % ncx);
-  if (threadIdx.x == 0) {
-    L.ctr[0] = 0;
-    L.ctr[1] = 0;
-  }
-  __syncthreads();
+  reset_counters(L);
   region_job<TX, TQ, R, SMAX, KAHAN>(a, region, q, L);
+  report_abort(L);
 }
 
 // A batch of images, one colour: a persistent grid walks the colour's work
@@ -609,13 +664,9 @@ __global__ __launch_bounds__(128) void region_phase_batch(const ImageDesc* __res
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
     const WorkItem w = items[it];
     if (ctl[w.img].done) continue;
-    if (threadIdx.x == 0) {
-      L.ctr[0] = 0;
-      L.ctr[1] = 0;
-    }
-    __syncthreads();
+    reset_counters(L);
     region_job<TX, TQ, R, SMAX, KAHAN>(imgs[w.img], w.region, q, L);
-    __syncthreads();
+    report_abort(L);
   }
 }
 

@@ -129,6 +129,16 @@ struct Plan {
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// A sweep kernel whose producer/consumer wait gave up sets g_wait_abort (a
+// protocol failure: the results are not trustworthy).
+int check_wait_abort(hipStream_t s) {
+  int v = 0;
+  HIP_OK(hipMemcpyFromSymbolAsync(&v, HIP_SYMBOL(g_wait_abort), sizeof v, 0,
+                                  hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  return v ? SMRE_EDEVICE : SMRE_OK;
+}
+
 int choose_region(int smax, int requested) {
   if (requested) return requested;
   if (smax <= 17) return 16;
@@ -171,8 +181,11 @@ int plan_project(smre_dtype dt, int64_t H, int64_t W, const smre_params* p, Plan
   pl->nrx = (int)((W + pl->R - 1) / pl->R);
   const size_t es = (p->inc == SMRE_INC_BF16) ? 2 : (dt == SMRE_F64 ? 8 : 4);
   const size_t xs = dt == SMRE_F64 ? 8 : 4;
-  // increments per region: each side s contributes s^2 per anchor in the region
-  int64_t nq = 0, nwin = 0;
+  // increments per region: each side s contributes s^2 per anchor in the region;
+  // every region starts on a page boundary of the stream (whole pages belong
+  // to one region, so the kernel writes them back without touching another's)
+  const int64_t page_elems = (int64_t)(kPage / es);
+  int64_t nq = 0, nq_stream = 0, nwin = 0;
   if (need_offsets) pl->roff.assign((size_t)pl->nry * pl->nrx + 1, 0);
   for (int ry = 0; ry < pl->nry; ++ry)
     for (int rx = 0; rx < pl->nrx; ++rx) {
@@ -184,13 +197,14 @@ int plan_project(smre_dtype dt, int64_t H, int64_t W, const smre_params* p, Plan
         cnt += s * s * ar * ac;
         nwin += ar * ac;
       }
-      if (need_offsets) pl->roff[(size_t)ry * pl->nrx + rx] = nq;
+      if (need_offsets) pl->roff[(size_t)ry * pl->nrx + rx] = nq_stream;
       nq += cnt;
+      nq_stream += (cnt + page_elems - 1) / page_elems * page_elems;
     }
-  if (need_offsets) pl->roff.back() = nq;
+  if (need_offsets) pl->roff.back() = nq_stream;
   pl->nq = nq;
   pl->nwin = nwin;
-  pl->qbytes = align_up((size_t)nq * es + kPage, 256);
+  pl->qbytes = align_up((size_t)nq_stream * es + kPage, kPage);
   pl->off_roff = pl->qbytes;
   pl->off_prev = align_up(pl->off_roff + ((size_t)pl->nry * pl->nrx + 1) * 8, 256);
   pl->total = align_up(pl->off_prev + (size_t)H * W * xs, 256);
@@ -378,6 +392,7 @@ int project_impl(smre_ctx* c, smre_dtype dt, void* x, int64_t H, int64_t W, int6
   if (rc) return rc;
   HIP_OK(hipEventRecord(c->t1, s));
   HIP_OK(hipEventSynchronize(c->t1));
+  if ((rc = check_wait_abort(s))) return rc;
   float ms = 0.f;
   HIP_OK(hipEventElapsedTime(&ms, c->t0, c->t1));
   if (rep) {
@@ -517,7 +532,7 @@ int plan_batch(smre_dtype dt, int n, const smre_batch_image* im, const smre_batc
     int rc = plan_project(dt, im[i].H, im[i].W, &p, &B->plans[i], need_offsets);
     if (rc) return rc;
     B->qoff[i] = B->qbytes;
-    B->qbytes += align_up(B->plans[i].qbytes, 256);
+    B->qbytes += align_up(B->plans[i].qbytes, kPage);
     B->roff_off[i] = B->roff_elems;
     B->roff_elems += (size_t)B->plans[i].nry * B->plans[i].nrx + 1;
     B->prev_off[i] = (int64_t)B->prev_elems;
@@ -876,6 +891,7 @@ int batch_impl(smre_ctx* c, smre_dtype dt, int n, const smre_batch_image* im,
     if (gx[g]) (void)hipGraphExecDestroy(gx[g]);
     if (gr[g]) (void)hipGraphDestroy(gr[g]);
   }
+  if ((rc = check_wait_abort(s))) return rc;
   std::vector<BatchCtl> ctl(n);
   HIP_OK(hipMemcpy(ctl.data(), D.ctl, sizeof(BatchCtl) * n, hipMemcpyDeviceToHost));
   HIP_OK(hipEventRecord(c->t1, s));
@@ -1161,6 +1177,7 @@ class HipBackend : public smre_serve::Backend {
     HIP_OK(hipMemcpyAsync(r.out.data(), sl.desc.x, r.out.size() * sizeof(float),
                           hipMemcpyDeviceToHost, stream_));
     HIP_OK(hipStreamSynchronize(stream_));
+    if (int rc = check_wait_abort(stream_)) return rc;
     std::memset(&r.rep, 0, sizeof r.rep);
     r.rep.sweeps = sl.last.done_sweep;
     r.rep.converged = sl.last.converged;
@@ -1221,14 +1238,16 @@ class HipBackend : public smre_serve::Backend {
   }
 
   // bytes of one request's block: increments (+ slack), region table, image, snapshot
+  // A request's slab: increments (page-aligned, first), region offsets, x,
+  // snapshot.  Sizes are whole pages so every slab starts on a page.
   size_t layout(const Plan& pl, const smre_serve::Request& r, size_t* offs) const {
-    size_t o = align_up(pl.qbytes, 256);
+    size_t o = align_up(pl.qbytes, kPage);
     if (offs) offs[0] = o;
     o = align_up(o + ((size_t)pl.nry * pl.nrx + 1) * 8, 256);
     if (offs) offs[1] = o;
     o = align_up(o + (size_t)r.H * r.W * 4, 256);
     if (offs) offs[2] = o;
-    o = align_up(o + (size_t)r.H * r.W * 4, 256);
+    o = align_up(o + (size_t)r.H * r.W * 4, kPage);
     return o;
   }
 
