@@ -372,128 +372,155 @@ __device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs
   const double r2d = a.r2d[k];
   __asm__ volatile("" : "+v"(r2), "+v"(rfl), "+v"(gr2));
 
-  for (int ap = 0; ap < S; ++ap) {
-    const int nr = (rhi - ap + S - 1) / S;
-    if (ap >= rhi) break;
-    for (int bp = 0; bp < S; ++bp) {
-      if (bp >= chi) break;
-      const int nc = (chi - bp + S - 1) / S;
-      for (int rby = 0; rby < nr; rby += BR) {
-        const int nbr = min(BR, nr - rby);
-        for (int rbx = 0; rbx < nc; rbx += BC) {
-          const int nbc = min(BC, nc - rbx);
-          const int nwr = nbr * nbc;
-          const bool valid = bry < nbr && brx < nbc;
-          const int woff = (bry * nbc + brx) * (S * S);
-          const uint32_t rb = c.qb;
-          const uint32_t nbytes = (uint32_t)(nwr * S * S * ES);
-          c.qb += nbytes;
-          // wait until every page holding this round's bytes is in the ring
-          const int need = (int)((c.qb + kPage - 1) / kPage);
-          if (need > c.ready_seen) c.ready_seen = wait_ge(c.ready, need, c.abort);
-          __asm__ volatile("" ::: "memory");
-          const uint32_t roff = rb & RMASK;
-          // ring offsets of the lane's elements (full / last column slot); the
-          // writes of masked lanes go to the dummy area
-          const uint32_t qf = roff + (uint32_t)((woff + ef) * ES);
-          const uint32_t ql = roff + (uint32_t)((woff + el) * ES);
-          const uint32_t wff = valid ? qf : (uint32_t)LS::QD;
-          const uint32_t wfl = valid && cl ? ql : (uint32_t)LS::QD;
-          const uint32_t wlf = valid && rl ? qf : (uint32_t)LS::QD;
-          const uint32_t wll = valid && rl && cl ? ql : (uint32_t)LS::QD;
-          const int bx = lane_x0 + (ap + S * rby) * P + (bp + S * rbx);
-          const int bxr = valid ? bx : 0;
-          const int bxw = valid ? bx : LS::XDUMMY;
-          const int bxw_r = valid && rl ? bx : LS::XDUMMY;
-          const int bxw_c = valid && cl ? bx : LS::XDUMMY;
-          const int bxw_rc = valid && rl && cl ? bx : LS::XDUMMY;
+  // Rounds of this side in visiting order -- offsets (ap, bp) raster, then
+  // row / column blocks of windows -- as one flat loop: the indices advance
+  // with scalar selects, so a round ends in a single backward branch.
+  constexpr bool MR = SS::RB > 1, MC = SS::CB > 1;  // more than one block per row / column
+  // region extents packed in one scalar (each < 256): anchors rows / cols,
+  // offsets rows / cols
+  const uint32_t ext = (uint32_t)rhi | ((uint32_t)chi << 8) | ((uint32_t)min(S, rhi) << 16) |
+                       ((uint32_t)min(S, chi) << 24);
+  uint32_t ap = 0, bp = 0, rby = 0, rbx = 0;
+  uint32_t nr = ((uint32_t)rhi + S - 1) / S, nc = ((uint32_t)chi + S - 1) / S;
+  do {
+    const int nbr = MR ? min(BR, (int)(nr - rby)) : (int)nr;
+    const int nbc = MC ? min(BC, (int)(nc - rbx)) : (int)nc;
+    const int nwr = nbr * nbc;
+    const bool valid = bry < nbr && brx < nbc;
+    const int woff = (bry * nbc + brx) * (S * S);
+    const uint32_t rb = c.qb;
+    const uint32_t nbytes = (uint32_t)(nwr * S * S * ES);
+    c.qb += nbytes;
+    // wait until every page holding this round's bytes is in the ring
+    const int need = (int)((c.qb + kPage - 1) / kPage);
+    if (__builtin_expect(need > c.ready_seen, 0)) c.ready_seen = wait_ge(c.ready, need, c.abort);
+    __asm__ volatile("" ::: "memory");
+    const uint32_t roff = rb & RMASK;
+    // ring offsets of the lane's elements (full / last column slot); the
+    // writes of masked lanes go to the dummy area
+    const uint32_t qf = roff + (uint32_t)((woff + ef) * ES);
+    const uint32_t ql = roff + (uint32_t)((woff + el) * ES);
+    const uint32_t wff = valid ? qf : (uint32_t)LS::QD;
+    const uint32_t wfl = valid && cl ? ql : (uint32_t)LS::QD;
+    const uint32_t wlf = valid && rl ? qf : (uint32_t)LS::QD;
+    const uint32_t wll = valid && rl && cl ? ql : (uint32_t)LS::QD;
+    const int bx = lane_x0 + (int)((ap + S * rby) * P + (bp + S * rbx));
+    const int bxr = valid ? bx : 0;
+    const int bxw = valid ? bx : LS::XDUMMY;
+    const int bxw_r = valid && rl ? bx : LS::XDUMMY;
+    const int bxw_c = valid && cl ? bx : LS::XDUMMY;
+    const int bxw_rc = valid && rl && cl ? bx : LS::XDUMMY;
 
-          // 1) LDS reads: pixels at immediates off one base, increments off two
-          TX xv[U][V], qv[U][V];
+    // 1) LDS reads: pixels at immediates off one base, increments off two
+    TX xv[U][V], qv[U][V];
 #pragma unroll
-          for (int u = 0; u < U; ++u)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int v = 0; v < V; ++v) {
-              qv[u][v] = QS::get(c.ring + (v == V - 1 ? ql : qf) + SS::slot(u, v) * ES);
-              xv[u][v] = xs[bxr + u * GR * P + v * GC];
-            }
-          // 2) y = x + I (pixels outside the window count as 0), sum of squares
-          TX y[U][V];
-          TX acc = 0, comp = 0;
+      for (int v = 0; v < V; ++v) {
+        qv[u][v] = QS::get(c.ring + (v == V - 1 ? ql : qf) + SS::slot(u, v) * ES);
+        xv[u][v] = xs[bxr + u * GR * P + v * GC];
+      }
+    // 2) y = x + I (pixels outside the window count as 0), sum of squares
+    TX y[U][V];
+    TX acc = 0, comp = 0;
 #pragma unroll
-          for (int u = 0; u < U; ++u)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int v = 0; v < V; ++v) {
-              TX yv = xv[u][v] + qv[u][v];
-              const bool part_r = (u == U - 1) && (JRL < GR);
-              const bool part_c = (v == V - 1) && (JCL < GC);
-              if (part_r && part_c) yv = (rl && cl) ? yv : TX(0);
-              else if (part_r) yv = rl ? yv : TX(0);
-              else if (part_c) yv = cl ? yv : TX(0);
-              y[u][v] = yv;
-              if constexpr (sizeof(TX) == 4 && KAHAN) {
-                const TX t2 = __builtin_fmaf(yv, yv, -comp);
-                const TX s2 = acc + t2;
-                comp = (s2 - acc) - t2;
-                acc = s2;
-              } else if constexpr (sizeof(TX) == 4) {
-                acc = __builtin_fmaf(yv, yv, acc);
-              } else {
-                acc = __builtin_fma(yv, yv, acc);
-              }
-            }
-          if constexpr (sizeof(TX) == 4 && KAHAN) acc -= comp;
-          const TX n = group_sum<G>(acc);
-
-          // 3) x' = t y into the footprint, I' = y - x' into the ring
-          auto write_step = [&](TX t) {
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-#pragma unroll
-              for (int v = 0; v < V; ++v) {
-                const bool part_r = (u == U - 1) && (JRL < GR);
-                const bool part_c = (v == V - 1) && (JCL < GC);
-                const int base = (part_r && part_c) ? bxw_rc : part_r ? bxw_r : part_c ? bxw_c : bxw;
-                const uint32_t wq = (u == U - 1 && JRL < GR) ? ((v == V - 1) ? wll : wlf)
-                                                            : ((v == V - 1) ? wfl : wff);
-                const TX xn = t * y[u][v];
-                xs[base + u * GR * P + v * GC] = xn;
-                QS::put(c.ring + wq + SS::slot(u, v) * ES, y[u][v] - xn);
-              }
-          };
-          if constexpr (sizeof(TX) == 4) {
-            // FP32 scale; windows whose sum lies within the guard band of the
-            // bound are redone with an FP64 sum after the writes
-            const bool near = fabsf(n - r2) <= gr2;
-            uint64_t nearmask = __ballot(near);
-            __asm__ volatile("" : "+s"(nearmask) :: "memory");
-            write_step(n > r2 ? rfl * __builtin_amdgcn_rsqf(n) : 1.0f);
-            if (nearmask) {
-              double pd = 0.0;
-#pragma unroll
-              for (int u = 0; u < U; ++u)
-#pragma unroll
-                for (int v = 0; v < V; ++v)
-                  pd = __builtin_fma((double)y[u][v], (double)y[u][v], pd);
-              const double nd = group_sum<G>(pd);
-              const float t64 = nd > r2d ? (float)__builtin_sqrt(r2d / nd) : 1.0f;
-              write_step(near ? t64 : (n > r2 ? rfl * __builtin_amdgcn_rsqf(n) : 1.0f));
-            }
-          } else {
-            write_step(n > r2 ? __builtin_sqrt(r2 / n) : TX(1));
-          }
-          // a round that ran into the mirrored pages copies them back
-          if (roff + nbytes > (uint32_t)(kSlots * kPage)) {
-            const int np = (int)((roff + nbytes - kSlots * kPage + kPage - 1) / kPage);
-            u32x4* r4 = (u32x4*)c.ring;
-            for (int p = 0; p < np; ++p) r4[p * 64 + c.lane] = r4[(kSlots + p) * 64 + c.lane];
-          }
-          __asm__ volatile("" ::: "memory");
-          lds_store(c.consumed, (int)(c.qb / kPage));
+      for (int v = 0; v < V; ++v) {
+        TX yv = xv[u][v] + qv[u][v];
+        const bool part_r = (u == U - 1) && (JRL < GR);
+        const bool part_c = (v == V - 1) && (JCL < GC);
+        if (part_r && part_c) yv = (rl && cl) ? yv : TX(0);
+        else if (part_r) yv = rl ? yv : TX(0);
+        else if (part_c) yv = cl ? yv : TX(0);
+        y[u][v] = yv;
+        if constexpr (sizeof(TX) == 4 && KAHAN) {
+          const TX t2 = __builtin_fmaf(yv, yv, -comp);
+          const TX s2 = acc + t2;
+          comp = (s2 - acc) - t2;
+          acc = s2;
+        } else if constexpr (sizeof(TX) == 4) {
+          acc = __builtin_fmaf(yv, yv, acc);
+        } else {
+          acc = __builtin_fma(yv, yv, acc);
         }
       }
+    if constexpr (sizeof(TX) == 4 && KAHAN) acc -= comp;
+    const TX n = group_sum<G>(acc);
+
+    // 3) x' = t y into the footprint, I' = y - x' into the ring (pixels
+    //    first, then increments, so neighbouring writes merge)
+    auto write_step = [&](TX t) {
+      TX xn[U][V];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const bool part_r = (u == U - 1) && (JRL < GR);
+          const bool part_c = (v == V - 1) && (JCL < GC);
+          const int base = (part_r && part_c) ? bxw_rc : part_r ? bxw_r : part_c ? bxw_c : bxw;
+          xn[u][v] = t * y[u][v];
+          xs[base + u * GR * P + v * GC] = xn[u][v];
+        }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const uint32_t wq = (u == U - 1 && JRL < GR) ? ((v == V - 1) ? wll : wlf)
+                                                      : ((v == V - 1) ? wfl : wff);
+          QS::put(c.ring + wq + SS::slot(u, v) * ES, y[u][v] - xn[u][v]);
+        }
+    };
+    if constexpr (sizeof(TX) == 4) {
+      // FP32 scale; windows whose sum lies within the guard band of the
+      // bound are redone with an FP64 sum after the writes
+      const bool near = fabsf(n - r2) <= gr2;
+      uint64_t nearmask = __ballot(near);
+      __asm__ volatile("" : "+s"(nearmask) :: "memory");
+      write_step(n > r2 ? rfl * __builtin_amdgcn_rsqf(n) : 1.0f);
+      if (__builtin_expect(nearmask != 0, 0)) {
+        double pd = 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int v = 0; v < V; ++v)
+            pd = __builtin_fma((double)y[u][v], (double)y[u][v], pd);
+        const double nd = group_sum<G>(pd);
+        const float t64 = nd > r2d ? (float)__builtin_sqrt(r2d / nd) : 1.0f;
+        write_step(near ? t64 : (n > r2 ? rfl * __builtin_amdgcn_rsqf(n) : 1.0f));
+      }
+    } else {
+      write_step(n > r2 ? __builtin_sqrt(r2 / n) : TX(1));
     }
-  }
+    // a round that ran into the mirrored pages copies them back
+    if (__builtin_expect(roff + nbytes > (uint32_t)(kSlots * kPage), 0)) {
+      const int np = (int)((roff + nbytes - kSlots * kPage + kPage - 1) / kPage);
+      u32x4* r4 = (u32x4*)c.ring;
+      for (int p = 0; p < np; ++p) r4[p * 64 + c.lane] = r4[(kSlots + p) * 64 + c.lane];
+    }
+    __asm__ volatile("" ::: "memory");
+    lds_store(c.consumed, (int)(c.qb / kPage));
+
+    // advance to the next round
+    bool wrap = true;
+    if constexpr (MC) {
+      rbx += BC;
+      wrap = rbx >= nc;
+      rbx = wrap ? 0 : rbx;
+    }
+    if constexpr (MR) {
+      rby = wrap ? rby + BR : rby;
+      const bool wy = rby >= nr;
+      rby = wy ? 0 : rby;
+      wrap = wy;
+    }
+    bp = wrap ? bp + 1 : bp;
+    const bool wb = bp >= (ext >> 24);
+    bp = wb ? 0 : bp;
+    ap = wb ? ap + 1 : ap;
+    nr = ((ext & 0xFF) - ap + S - 1) / S;
+    nc = (((ext >> 8) & 0xFF) - bp + S - 1) / S;
+  } while (ap < ((ext >> 16) & 0xFF));
 }
 
 template <typename TX, typename TQ, int R, int SMAX, bool KAHAN>
