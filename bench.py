@@ -331,6 +331,9 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--max-active", type=int, default=16)
     ap.add_argument("--serve-baseline", action="store_true")
+    ap.add_argument("--guard", type=float, default=1e-5,
+                    help="relative band around the bound in which FP32 window sums are "
+                         "rechecked in FP64")
     ap.add_argument("--profile-sweeps", type=int, default=0,
                     help="counter-collection mode: one 1 GiB device copy (the calibration "
                          "kernel), then this many sweeps of the workload; no timing line")
@@ -364,7 +367,7 @@ def main():
     ctx = smre.Context(0)
     ctx.set_timing(True)
     opts = smre.ProjectOptions(tol=wl["tol"], max_sweeps=wl["max_sweeps"], check_every=1,
-                               region=args.region, kahan=True, guard_rel=1e-5,
+                               region=args.region, kahan=True, guard_rel=args.guard,
                                inc=smre.INC_BF16 if wl["inc"] == "bf16" else smre.INC_SAME)
 
     def step():
@@ -382,7 +385,8 @@ def main():
         del a, b
         x.copy_(x0_dev)
         prof = smre.ProjectOptions(tol=0.0, max_sweeps=args.profile_sweeps, check_every=1,
-                                   region=args.region, kahan=True, guard_rel=1e-5, inc=opts.inc)
+                                   region=args.region, kahan=True, guard_rel=args.guard,
+                                   inc=opts.inc)
         rc, rep = ctx.project(x, sides, r2, prof)
         torch.cuda.synchronize()
         print(json.dumps({"profile_sweeps": rep["sweeps"], "kernel_launches":
@@ -427,7 +431,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": wl["workload"], "H": H, "W": W, "sides": f"1..{sides[-1]}",
-                   "tol": wl["tol"], "increments": wl["inc"], "region": reps[0]["region"]},
+                   "tol": wl["tol"], "increments": wl["inc"], "region": reps[0]["region"],
+                   "guard_rel": args.guard},
         "time_to_tol_ms": el / args.steps * 1e3,
         "sweeps_to_tol": sweeps,
         "converged": all(r["converged"] for r in reps),

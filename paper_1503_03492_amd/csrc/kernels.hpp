@@ -15,9 +15,10 @@
 //     phase and runs the steps: y = x + I, n = sum y^2 per window (lanes of a
 //     window reduce with DPP / permlane swaps), t = sqrt(r2/n) if n > r2,
 //     x' = t y, I' = y - x'.  I' is written back into the ring in place.
-//   wave 1 (producer) streams the region's increments -- one page-aligned
-//     contiguous byte range of the increment buffer per region and sweep --
-//     through a ring of 1 KiB pages in LDS, several loads in flight, and
+//   wave 1 (producer) streams the region's increments -- a sequence of whole
+//     1 KiB pages per region and sweep, interleaved in HBM with the pages of
+//     the other regions of its colour -- through a ring of pages in LDS,
+//     several loads in flight, and
 //     writes every page the consumer has finished back to HBM with 16-byte
 //     stores before its slot is reused.  The first pages of the ring are
 //     mirrored after its end so a round's chunk is always a linear LDS range
@@ -34,10 +35,11 @@
 // area instead of branching, and the FP64 guard-band recheck branches after
 // the writes it may redo.
 //
-// Increment layout: per region (raster order, each region starting on a page
-// boundary), its steps in visiting order; per step, rounds of up to BR x BC
+// Increment layout: each region's increments form one stream of whole 1 KiB
+// pages -- its steps in visiting order; per step, rounds of up to BR x BC
 // windows; per round, the valid windows in row-major order, S^2 elements each,
-// ordered by slot (u, v) then lane.
+// ordered by slot (u, v) then lane.  The pages of the regions of one colour
+// are interleaved in HBM (RegionStream).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -280,11 +282,22 @@ __device__ __forceinline__ void lds_store(int* p, int v) {
 }
 
 // ---------------------------------------------------------------- phase kernel
+// Where a region's increment pages lie: page p at first + p * stride (pages
+// of the image's stream).  The regions of one colour interleave their pages
+// (stride = regions of the colour), so the workgroups of a launch stream one
+// contiguous window of HBM at a time.
+struct RegionStream {
+  int32_t first;
+  int32_t npages;
+  int32_t stride;
+  int32_t pad;
+};
+
 // Everything a region job needs about its image.  Passed by value for a
 // single image; an array in device memory for a batch.
 struct ImageDesc {
-  void* x;              // image (TX), row stride ld
-  const int64_t* roff;  // increment offset (elements, from q_byte) of each region, +1 sentinel
+  void* x;                 // image (TX), row stride ld
+  const RegionStream* rs;  // page layout of each region's increments
   int64_t ld;
   int64_t q_byte;       // first byte of this image's increments in the stream
   int32_t H, W;
@@ -544,22 +557,23 @@ __device__ __forceinline__ void dispatch_side(const ImageDesc& a, Consumer& c, T
 }
 
 // Producer wave: stream pages [0, npg) of the region's increments (gq points
-// at its first page) into the ring (slot = page mod kSlots; slots below MIRROR
+// at its first page, page p at gq + p * stride pages) into the ring (slot = page mod kSlots; slots below MIRROR
 // also after the ring end), kPrefetch loads in flight.  A slot is refilled
 // only after its previous page has been written back to HBM, and a page is
 // written back (one 16-byte store per lane) once the consumer has finished
 // it.  Full batches of kPrefetch pages run branch-free so the loads stay in
 // flight across batches.
 template <int MIRROR>
-__device__ __forceinline__ void produce(u32x4* gq, int npg, u32x4* ring, int* ready,
-                                        const int* consumed, int* abort, int lane) {
+__device__ __forceinline__ void produce(u32x4* gq, int npg, int64_t stride, u32x4* ring,
+                                        int* ready, const int* consumed, int* abort, int lane) {
   if (npg <= 0) return;
+  stride *= 64;  // in 16-byte units
   int cons_seen = 0, wb = 0;
   auto writeback = [&]() {
     if (wb >= cons_seen) cons_seen = wait_ge(consumed, wb + 1, abort);
     __asm__ volatile("" ::: "memory");
     const u32x4 v = ring[(wb & (kSlots - 1)) * 64 + lane];
-    __builtin_nontemporal_store(v, gq + (int64_t)wb * 64 + lane);
+    __builtin_nontemporal_store(v, gq + (int64_t)wb * stride + lane);
     ++wb;
   };
   auto put = [&](int rel, u32x4 v) {
@@ -573,14 +587,14 @@ __device__ __forceinline__ void produce(u32x4* gq, int npg, u32x4* ring, int* re
   u32x4 buf[kPrefetch];
 #pragma unroll
   for (int k = 0; k < kPrefetch; ++k)
-    buf[k] = __builtin_nontemporal_load(gq + (int64_t)min(k, npg - 1) * 64 + lane);
+    buf[k] = __builtin_nontemporal_load(gq + (int64_t)min(k, npg - 1) * stride + lane);
   int base = 0;
   for (; base + kPrefetch <= npg; base += kPrefetch) {
 #pragma unroll
     for (int k = 0; k < kPrefetch; ++k) {
       const int rel = base + k;
       put(rel, buf[k]);
-      buf[k] = __builtin_nontemporal_load(gq + (int64_t)min(rel + kPrefetch, npg - 1) * 64 + lane);
+      buf[k] = __builtin_nontemporal_load(gq + (int64_t)min(rel + kPrefetch, npg - 1) * stride + lane);
     }
   }
 #pragma unroll
@@ -607,15 +621,13 @@ __device__ __forceinline__ void region_job(const ImageDesc& a, int region, unsig
                                            PhaseLds<TX, TQ, R, SMAX>& L) {
   using SH = PhaseShape<TX, TQ, R, SMAX>;
   const int ry = region / a.nrx, rx = region - (region / a.nrx) * a.nrx;
-  // regions start on a page boundary of the increment stream
-  const int64_t byte_lo = a.q_byte + a.roff[region] * (int64_t)sizeof(TQ);
-  const int64_t byte_hi = a.q_byte + a.roff[region + 1] * (int64_t)sizeof(TQ);
-  const int npg = (int)((byte_hi - byte_lo + kPage - 1) / kPage);
+  const RegionStream st = a.rs[region];
+  const int npg = st.npages;
   const int lane = threadIdx.x & 63;
 
   if (threadIdx.x >= 64) {
-    produce<SH::MIRROR>((u32x4*)(q + byte_lo), npg, (u32x4*)L.ring, &L.ctr[0], &L.ctr[1],
-                        &L.ctr[2], lane);
+    produce<SH::MIRROR>((u32x4*)(q + a.q_byte) + (int64_t)st.first * 64, npg, st.stride,
+                        (u32x4*)L.ring, &L.ctr[0], &L.ctr[1], &L.ctr[2], lane);
     return;
   }
 

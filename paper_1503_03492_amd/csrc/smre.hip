@@ -124,7 +124,7 @@ struct Plan {
   int64_t nwin = 0;
   size_t qbytes = 0;
   size_t off_roff = 0, off_prev = 0, total = 0;
-  std::vector<int64_t> roff;
+  std::vector<RegionStream> roff;  // page layout of each region's increments
 };
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -181,12 +181,15 @@ int plan_project(smre_dtype dt, int64_t H, int64_t W, const smre_params* p, Plan
   pl->nrx = (int)((W + pl->R - 1) / pl->R);
   const size_t es = (p->inc == SMRE_INC_BF16) ? 2 : (dt == SMRE_F64 ? 8 : 4);
   const size_t xs = dt == SMRE_F64 ? 8 : 4;
-  // increments per region: each side s contributes s^2 per anchor in the region;
-  // every region starts on a page boundary of the stream (whole pages belong
-  // to one region, so the kernel writes them back without touching another's)
-  const int64_t page_elems = (int64_t)(kPage / es);
-  int64_t nq = 0, nq_stream = 0, nwin = 0;
-  if (need_offsets) pl->roff.assign((size_t)pl->nry * pl->nrx + 1, 0);
+  // increments per region: each side s contributes s^2 per anchor in the
+  // region.  A region's increments occupy whole 1 KiB pages (so the kernel
+  // writes pages back without touching another region's); the pages of the
+  // regions of one colour are interleaved -- page p of the colour's b-th region
+  // (in launch order) at segment_base + p * (regions of the colour) + b -- so
+  // the workgroups of a launch stream one contiguous window of HBM.
+  const int nreg = pl->nry * pl->nrx;
+  std::vector<int32_t> npg((size_t)nreg, 0);
+  int64_t nq = 0, nwin = 0, maxpg[4] = {0, 0, 0, 0}, nb[4] = {0, 0, 0, 0};
   for (int ry = 0; ry < pl->nry; ++ry)
     for (int rx = 0; rx < pl->nrx; ++rx) {
       int64_t cnt = 0;
@@ -197,16 +200,36 @@ int plan_project(smre_dtype dt, int64_t H, int64_t W, const smre_params* p, Plan
         cnt += s * s * ar * ac;
         nwin += ar * ac;
       }
-      if (need_offsets) pl->roff[(size_t)ry * pl->nrx + rx] = nq_stream;
       nq += cnt;
-      nq_stream += (cnt + page_elems - 1) / page_elems * page_elems;
+      const int col = (ry & 1) * 2 + (rx & 1);
+      npg[(size_t)ry * pl->nrx + rx] = (int32_t)((cnt * (int64_t)es + kPage - 1) / kPage);
+      maxpg[col] = std::max<int64_t>(maxpg[col], npg[(size_t)ry * pl->nrx + rx]);
+      nb[col]++;
     }
-  if (need_offsets) pl->roff.back() = nq_stream;
+  int64_t seg[4], pages = 0;
+  for (int col = 0; col < 4; ++col) {
+    seg[col] = pages;
+    pages += maxpg[col] * nb[col];
+  }
+  if (pages >= (int64_t)1 << 31) return SMRE_ETOOBIG;
+  if (need_offsets) {
+    pl->roff.assign((size_t)nreg, RegionStream{0, 0, 0, 0});
+    for (int ry = 0; ry < pl->nry; ++ry)
+      for (int rx = 0; rx < pl->nrx; ++rx) {
+        const int cy = ry & 1, cx = rx & 1, col = cy * 2 + cx;
+        const int ncx = (pl->nrx - cx + 1) / 2;
+        const int64_t b = (int64_t)(ry >> 1) * ncx + (rx >> 1);
+        RegionStream& r = pl->roff[(size_t)ry * pl->nrx + rx];
+        r.first = (int32_t)(seg[col] + b);
+        r.npages = npg[(size_t)ry * pl->nrx + rx];
+        r.stride = (int32_t)nb[col];
+      }
+  }
   pl->nq = nq;
   pl->nwin = nwin;
-  pl->qbytes = align_up((size_t)nq_stream * es + kPage, kPage);
+  pl->qbytes = (size_t)(pages + 1) * kPage;
   pl->off_roff = pl->qbytes;
-  pl->off_prev = align_up(pl->off_roff + ((size_t)pl->nry * pl->nrx + 1) * 8, 256);
+  pl->off_prev = align_up(pl->off_roff + (size_t)nreg * sizeof(RegionStream), 256);
   pl->total = align_up(pl->off_prev + (size_t)H * W * xs, 256);
   return SMRE_OK;
 }
@@ -312,12 +335,12 @@ int project_impl(smre_ctx* c, smre_dtype dt, void* x, int64_t H, int64_t W, int6
   const int64_t nwords = (int64_t)(pl.qbytes / 4);
   hipLaunchKernelGGL((fill_kernel<uint32_t>), dim3(grid_for(nwords)), dim3(256), 0, s,
                      (uint32_t*)ws, nwords, 0u);
-  HIP_OK(hipMemcpyAsync(ws + pl.off_roff, pl.roff.data(), pl.roff.size() * 8,
+  HIP_OK(hipMemcpyAsync(ws + pl.off_roff, pl.roff.data(), pl.roff.size() * sizeof(RegionStream),
                         hipMemcpyHostToDevice, s));
 
   ImageDesc a{};
   a.x = x;
-  a.roff = (const int64_t*)(ws + pl.off_roff);
+  a.rs = (const RegionStream*)(ws + pl.off_roff);
   a.ld = ld;
   a.q_byte = 0;
   a.H = (int)H;
@@ -534,7 +557,7 @@ int plan_batch(smre_dtype dt, int n, const smre_batch_image* im, const smre_batc
     B->qoff[i] = B->qbytes;
     B->qbytes += align_up(B->plans[i].qbytes, kPage);
     B->roff_off[i] = B->roff_elems;
-    B->roff_elems += (size_t)B->plans[i].nry * B->plans[i].nrx + 1;
+    B->roff_elems += (size_t)B->plans[i].nry * B->plans[i].nrx;
     B->prev_off[i] = (int64_t)B->prev_elems;
     B->prev_elems += (size_t)(im[i].H * im[i].W);
     const Plan& pl = B->plans[i];
@@ -543,7 +566,7 @@ int plan_batch(smre_dtype dt, int n, const smre_batch_image* im, const smre_batc
     items_total += (int64_t)pl.nry * pl.nrx;
   }
   B->off_roff = B->qbytes;
-  B->off_desc = align_up(B->off_roff + B->roff_elems * 8, 256);
+  B->off_desc = align_up(B->off_roff + B->roff_elems * sizeof(RegionStream), 256);
   B->off_ctl = align_up(B->off_desc + sizeof(ImageDesc) * n, 256);
   B->off_items = align_up(B->off_ctl + sizeof(BatchCtl) * n, 256);
   B->off_cnt = align_up(B->off_items + sizeof(WorkItem) * items_total, 256);
@@ -648,7 +671,7 @@ int batch_setup(smre_ctx* c, smre_dtype dt, int n, const smre_batch_image* im,
   for (int c2 = 0; c2 < 4; ++c2) items_total += B.nitems[c2];
   host.assign(B.off_prev - B.off_roff, 0);
   unsigned char* h = host.data();
-  int64_t* roff = (int64_t*)(h + 0);
+  RegionStream* roff = (RegionStream*)(h + 0);
   ImageDesc* desc = (ImageDesc*)(h + (B.off_desc - B.off_roff));
   BatchCtl* ctl = (BatchCtl*)(h + (B.off_ctl - B.off_roff));
   WorkItem* items = (WorkItem*)(h + (B.off_items - B.off_roff));
@@ -662,7 +685,7 @@ int batch_setup(smre_ctx* c, smre_dtype dt, int n, const smre_batch_image* im,
     for (size_t k = 0; k < pl.roff.size(); ++k) roff[B.roff_off[i] + k] = pl.roff[k];
     ImageDesc& a = desc[i];
     a.x = im[i].x;
-    a.roff = (const int64_t*)(ws + B.off_roff) + B.roff_off[i];
+    a.rs = (const RegionStream*)(ws + B.off_roff) + B.roff_off[i];
     a.ld = im[i].ld;
     a.q_byte = (int64_t)B.qoff[i];
     a.H = (int)im[i].H;
@@ -1097,8 +1120,9 @@ class HipBackend : public smre_serve::Backend {
     HIP_OK(hipSetDevice(cfg_.device));
     HIP_OK(hipMemcpyAsync(base + off_x, r.in.data(), r.in.size() * sizeof(float),
                           hipMemcpyHostToDevice, stream_));
-    HIP_OK(hipMemcpyAsync(base + off_roff, sl.plan.roff.data(), sl.plan.roff.size() * 8,
-                          hipMemcpyHostToDevice, stream_));
+    HIP_OK(hipMemcpyAsync(base + off_roff, sl.plan.roff.data(),
+                          sl.plan.roff.size() * sizeof(RegionStream), hipMemcpyHostToDevice,
+                          stream_));
     const int64_t nwords = (int64_t)(sl.plan.qbytes / 4);
     hipLaunchKernelGGL((fill_kernel<uint32_t>), dim3(grid_for(nwords)), dim3(256), 0, stream_,
                        (uint32_t*)base, nwords, 0u);
@@ -1106,7 +1130,7 @@ class HipBackend : public smre_serve::Backend {
     ImageDesc& a = sl.desc;
     std::memset(&a, 0, sizeof a);
     a.x = base + off_x;
-    a.roff = (const int64_t*)(base + off_roff);
+    a.rs = (const RegionStream*)(base + off_roff);
     a.ld = r.W;
     a.q_byte = (int64_t)at;
     a.H = r.H;
@@ -1243,7 +1267,7 @@ class HipBackend : public smre_serve::Backend {
   size_t layout(const Plan& pl, const smre_serve::Request& r, size_t* offs) const {
     size_t o = align_up(pl.qbytes, kPage);
     if (offs) offs[0] = o;
-    o = align_up(o + ((size_t)pl.nry * pl.nrx + 1) * 8, 256);
+    o = align_up(o + (size_t)pl.nry * pl.nrx * sizeof(RegionStream), 256);
     if (offs) offs[1] = o;
     o = align_up(o + (size_t)r.H * r.W * 4, 256);
     if (offs) offs[2] = o;
