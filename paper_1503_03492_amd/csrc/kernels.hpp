@@ -167,7 +167,9 @@ template <typename TX, typename TQ, int R, int SMAX> struct PhaseShape {
     return m;
   }
   static constexpr int XDUMMY = XROWS * P;
-  static constexpr int XSIZE = XROWS * P + dummy();
+  // masked lanes write to XDUMMY + lane + immediate: distinct addresses, so
+  // the writes of a round's masked lanes do not serialise on one bank
+  static constexpr int XSIZE = XROWS * P + dummy() + 64;
   // mirrored ring pages: enough for the largest round read
   static constexpr int mirror() {
     int m = 0;
@@ -193,7 +195,7 @@ template <typename TX, typename TQ, int R, int SMAX> struct PhaseShape {
     return (m + 15) / 16 * 16;
   }
   static constexpr int QD = (kSlots + MIRROR) * kPage;  // ring byte offset of the dummy area
-  static constexpr int RING = QD + qdummy();
+  static constexpr int RING = QD + qdummy() + 64 * (int)sizeof(TQ);  // + one element per lane
   static_assert(MIRROR + 2 <= kSlots, "ring too small for a round");
 };
 
@@ -377,6 +379,9 @@ __device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs
   const bool rl = jr < JRL, cl = jc < JCL;     // lane holds a pixel in the last row / col slot
   const int ef = jr * GC + jc, el = jr * JCL + jc;  // element of the lane inside a slot
   const int lane_x0 = (S * bry + jr) * P + (S * brx + jc);
+  // per-lane dummy targets for the writes of masked lanes
+  const int xdum = LS::XDUMMY + c.lane;
+  const uint32_t qdum = (uint32_t)(LS::QD + c.lane * ES);
   const int rhi = min(R, a.H - S + 1 - c.r0), chi = min(R, a.W - S + 1 - c.c0);
   if (rhi <= 0 || chi <= 0) return;
   // per-side constants live in VGPRs (the loop would otherwise reload them)
@@ -413,16 +418,16 @@ __device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs
     // writes of masked lanes go to the dummy area
     const uint32_t qf = roff + (uint32_t)((woff + ef) * ES);
     const uint32_t ql = roff + (uint32_t)((woff + el) * ES);
-    const uint32_t wff = valid ? qf : (uint32_t)LS::QD;
-    const uint32_t wfl = valid && cl ? ql : (uint32_t)LS::QD;
-    const uint32_t wlf = valid && rl ? qf : (uint32_t)LS::QD;
-    const uint32_t wll = valid && rl && cl ? ql : (uint32_t)LS::QD;
+    const uint32_t wff = valid ? qf : qdum;
+    const uint32_t wfl = valid && cl ? ql : qdum;
+    const uint32_t wlf = valid && rl ? qf : qdum;
+    const uint32_t wll = valid && rl && cl ? ql : qdum;
     const int bx = lane_x0 + (int)((ap + S * rby) * P + (bp + S * rbx));
     const int bxr = valid ? bx : 0;
-    const int bxw = valid ? bx : LS::XDUMMY;
-    const int bxw_r = valid && rl ? bx : LS::XDUMMY;
-    const int bxw_c = valid && cl ? bx : LS::XDUMMY;
-    const int bxw_rc = valid && rl && cl ? bx : LS::XDUMMY;
+    const int bxw = valid ? bx : xdum;
+    const int bxw_r = valid && rl ? bx : xdum;
+    const int bxw_c = valid && cl ? bx : xdum;
+    const int bxw_rc = valid && rl && cl ? bx : xdum;
 
     // 1) LDS reads: pixels at immediates off one base, increments off two
     TX xv[U][V], qv[U][V];
