@@ -404,7 +404,8 @@ __device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs
     const int nbr = MR ? min(BR, (int)(nr - rby)) : (int)nr;
     const int nbc = MC ? min(BC, (int)(nc - rbx)) : (int)nc;
     const int nwr = nbr * nbc;
-    const bool valid = bry < nbr && brx < nbc;
+    // a round holds at least one window, so one-window blocks are always valid
+    const bool valid = (BR == 1 || bry < nbr) && (BC == 1 || brx < nbc);
     const int woff = (bry * nbc + brx) * (S * S);
     const uint32_t rb = c.qb;
     const uint32_t nbytes = (uint32_t)(nwr * S * S * ES);
@@ -536,8 +537,13 @@ __device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs
     const bool wb = bp >= (ext >> 24);
     bp = wb ? 0 : bp;
     ap = wb ? ap + 1 : ap;
-    nr = ((ext & 0xFF) - ap + S - 1) / S;
-    nc = (((ext >> 8) & 0xFF) - bp + S - 1) / S;
+    if constexpr (2 * S >= R) {  // at most two windows per region row / column
+      nr = 1 + (ap + S < (ext & 0xFF));
+      nc = 1 + (bp + S < ((ext >> 8) & 0xFF));
+    } else {
+      nr = ((ext & 0xFF) - ap + S - 1) / S;
+      nc = (((ext >> 8) & 0xFF) - bp + S - 1) / S;
+    }
   } while (ap < ((ext >> 16) & 0xFF));
 }
 
