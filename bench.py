@@ -250,7 +250,6 @@ def bench_icd(args):
         reps.append(ctx.incomplete(x, K, r2, tol=1e-3, mode=smre.TOL_MEANABS, max_inner=10000))
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    copy_gbs = copy_bandwidth(torch, dev)
     wp = sum(r["window_projections"] for r in reps)
     kms = sum(r["kernel_ms"] for r in reps)
     by = sum(r["bytes_moved"] for r in reps)

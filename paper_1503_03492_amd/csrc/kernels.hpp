@@ -295,11 +295,28 @@ struct RegionStream {
   int32_t pad;
 };
 
+// One round of a side's visiting order in a region (see the round tables
+// below): x = pixel offset of the round's first window in the footprint (bits
+// 0..15) | windows of the round along a row of windows (bits 16..19) | along
+// a column (bits 20..23); y = end of the round's increment bytes, counted
+// from the side's first byte.
+struct RoundEntry {
+  uint32_t x, y;
+};
+
+// Round tables: for each side k and border class (row class * 3 + column
+// class; class 0 = interior region, 1 = next-to-last, 2 = last region row or
+// column), R * R + 2 entries: entry 0 = {number of rounds, 0}, entry 1 unused,
+// entries 2.. the rounds in visiting order.  Built on the host from the same
+// enumeration the oracle's region order uses.
+__host__ __device__ constexpr int round_table_len(int R) { return R * R + 2; }
+
 // Everything a region job needs about its image.  Passed by value for a
 // single image; an array in device memory for a batch.
 struct ImageDesc {
   void* x;                 // image (TX), row stride ld
   const RegionStream* rs;  // page layout of each region's increments
+  const RoundEntry* rtab;  // round tables, [side][class][round_table_len(R)]
   int64_t ld;
   int64_t q_byte;       // first byte of this image's increments in the stream
   int32_t H, W;
@@ -364,7 +381,8 @@ struct Consumer {
 };
 
 template <typename TX, typename TQ, int R, int SMAX, int S, bool KAHAN>
-__device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs, int k) {
+__device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs, int k,
+                                         const RoundEntry* tab, int nrounds) {
   using SS = SideShape<R, S>;
   using LS = PhaseShape<TX, TQ, R, SMAX>;
   constexpr int GR = SS::GR, GC = SS::GC, G = SS::G, BR = SS::BR, BC = SS::BC;
@@ -382,8 +400,7 @@ __device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs
   // per-lane dummy targets for the writes of masked lanes
   const int xdum = LS::XDUMMY + c.lane;
   const uint32_t qdum = (uint32_t)(LS::QD + c.lane * ES);
-  const int rhi = min(R, a.H - S + 1 - c.r0), chi = min(R, a.W - S + 1 - c.c0);
-  if (rhi <= 0 || chi <= 0) return;
+  if (nrounds <= 0) return;
   // per-side constants live in VGPRs (the loop would otherwise reload them)
   TX r2 = (sizeof(TX) == 8) ? (TX)a.r2d[k] : (TX)a.r2f[k];
   float rfl = a.rf[k], gr2 = a.guard * a.r2f[k];
@@ -391,30 +408,27 @@ __device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs
   __asm__ volatile("" : "+v"(r2), "+v"(rfl), "+v"(gr2));
 
   // Rounds of this side in visiting order -- offsets (ap, bp) raster, then
-  // row / column blocks of windows -- as one flat loop: the indices advance
-  // with scalar selects, so a round ends in a single backward branch.
-  constexpr bool MR = SS::RB > 1, MC = SS::CB > 1;  // more than one block per row / column
-  // region extents packed in one scalar (each < 256): anchors rows / cols,
-  // offsets rows / cols
-  const uint32_t ext = (uint32_t)rhi | ((uint32_t)chi << 8) | ((uint32_t)min(S, rhi) << 16) |
-                       ((uint32_t)min(S, chi) << 24);
-  uint32_t ap = 0, bp = 0, rby = 0, rbx = 0;
-  uint32_t nr = ((uint32_t)rhi + S - 1) / S, nc = ((uint32_t)chi + S - 1) / S;
+  // row / column blocks of windows -- read from the region's round table in
+  // LDS, one entry per round (the next entry is read a round ahead).
+  const uint32_t qb0 = c.qb;
+  uint32_t rb = 0;
+  RoundEntry e = tab[0];
+  int i = 0;
   do {
-    const int nbr = MR ? min(BR, (int)(nr - rby)) : (int)nr;
-    const int nbc = MC ? min(BC, (int)(nc - rbx)) : (int)nc;
-    const int nwr = nbr * nbc;
-    // a round holds at least one window, so one-window blocks are always valid
+    const RoundEntry en = tab[i + 1];  // entry past the last one is in the buffer, unused
+    const uint32_t rb_end = __builtin_amdgcn_readfirstlane(e.y);
+    const uint32_t nbytes = rb_end - rb;
+    int nbr = 1, nbc = 1;
+    if constexpr (BR > 1) nbr = (int)((e.x >> 20) & 0xF);
+    if constexpr (BC > 1) nbc = (int)((e.x >> 16) & 0xF);
+    // one-window blocks are always valid (a round holds at least one window)
     const bool valid = (BR == 1 || bry < nbr) && (BC == 1 || brx < nbc);
     const int woff = (bry * nbc + brx) * (S * S);
-    const uint32_t rb = c.qb;
-    const uint32_t nbytes = (uint32_t)(nwr * S * S * ES);
-    c.qb += nbytes;
     // wait until every page holding this round's bytes is in the ring
-    const int need = (int)((c.qb + kPage - 1) / kPage);
+    const int need = (int)((qb0 + rb_end + kPage - 1) / kPage);
     if (__builtin_expect(need > c.ready_seen, 0)) c.ready_seen = wait_ge(c.ready, need, c.abort);
     __asm__ volatile("" ::: "memory");
-    const uint32_t roff = rb & RMASK;
+    const uint32_t roff = (qb0 + rb) & RMASK;
     // ring offsets of the lane's elements (full / last column slot); the
     // writes of masked lanes go to the dummy area
     const uint32_t qf = roff + (uint32_t)((woff + ef) * ES);
@@ -423,7 +437,7 @@ __device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs
     const uint32_t wfl = valid && cl ? ql : qdum;
     const uint32_t wlf = valid && rl ? qf : qdum;
     const uint32_t wll = valid && rl && cl ? ql : qdum;
-    const int bx = lane_x0 + (int)((ap + S * rby) * P + (bp + S * rbx));
+    const int bx = lane_x0 + (int)(e.x & 0xFFFF);
     const int bxr = valid ? bx : 0;
     const int bxw = valid ? bx : xdum;
     const int bxw_r = valid && rl ? bx : xdum;
@@ -518,41 +532,20 @@ __device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs
       for (int p = 0; p < np; ++p) r4[p * 64 + c.lane] = r4[(kSlots + p) * 64 + c.lane];
     }
     __asm__ volatile("" ::: "memory");
-    lds_store(c.consumed, (int)(c.qb / kPage));
-
-    // advance to the next round
-    bool wrap = true;
-    if constexpr (MC) {
-      rbx += BC;
-      wrap = rbx >= nc;
-      rbx = wrap ? 0 : rbx;
-    }
-    if constexpr (MR) {
-      rby = wrap ? rby + BR : rby;
-      const bool wy = rby >= nr;
-      rby = wy ? 0 : rby;
-      wrap = wy;
-    }
-    bp = wrap ? bp + 1 : bp;
-    const bool wb = bp >= (ext >> 24);
-    bp = wb ? 0 : bp;
-    ap = wb ? ap + 1 : ap;
-    if constexpr (2 * S >= R) {  // at most two windows per region row / column
-      nr = 1 + (ap + S < (ext & 0xFF));
-      nc = 1 + (bp + S < ((ext >> 8) & 0xFF));
-    } else {
-      nr = ((ext & 0xFF) - ap + S - 1) / S;
-      nc = (((ext >> 8) & 0xFF) - bp + S - 1) / S;
-    }
-  } while (ap < ((ext >> 16) & 0xFF));
+    lds_store(c.consumed, (int)((qb0 + rb_end) / kPage));
+    rb = rb_end;
+    e = en;
+  } while (++i < nrounds);
+  c.qb = qb0 + rb;
 }
 
 template <typename TX, typename TQ, int R, int SMAX, bool KAHAN>
-__device__ __forceinline__ void dispatch_side(const ImageDesc& a, Consumer& c, TX* xs, int k) {
+__device__ __forceinline__ void dispatch_side(const ImageDesc& a, Consumer& c, TX* xs, int k,
+                                              const RoundEntry* tab, int nrounds) {
   switch (a.sides[k]) {
 #define SMRE_SIDE_CASE(n) \
   case n:                 \
-    if constexpr (n <= SMAX) run_side<TX, TQ, R, SMAX, n, KAHAN>(a, c, xs, k); \
+    if constexpr (n <= SMAX) run_side<TX, TQ, R, SMAX, n, KAHAN>(a, c, xs, k, tab, nrounds); \
     break;
     SMRE_SIDE_CASE(1) SMRE_SIDE_CASE(2) SMRE_SIDE_CASE(3) SMRE_SIDE_CASE(4) SMRE_SIDE_CASE(5)
     SMRE_SIDE_CASE(6) SMRE_SIDE_CASE(7) SMRE_SIDE_CASE(8) SMRE_SIDE_CASE(9) SMRE_SIDE_CASE(10)
@@ -618,6 +611,7 @@ template <typename TX, typename TQ, int R, int SMAX> struct PhaseLds {
   using SH = PhaseShape<TX, TQ, R, SMAX>;
   unsigned char ring[SH::RING];
   TX xs[SH::XSIZE];
+  RoundEntry tab[R * R + 2];  // the current side's rounds (+ one readable entry past the end)
   int ctr[3];  // pages ready, pages consumed, abort flag
 };
 
@@ -662,8 +656,36 @@ __device__ __forceinline__ void region_job(const ImageDesc& a, int region, unsig
   c.c0 = c0;
   c.lane = lane;
   c.ready_seen = 0;
-  for (int k = 0; k < a.nsides; ++k) dispatch_side<TX, TQ, R, SMAX, KAHAN>(a, c, xs, k);
-  __asm__ volatile("" ::: "memory");
+  // round tables: the next side's table is loaded into registers while the
+  // current side runs and parked in LDS between sides
+  const int cls = (ry == a.nry - 1 ? 2 : ry == a.nry - 2 ? 1 : 0) * 3 +
+                  (rx == a.nrx - 1 ? 2 : rx == a.nrx - 2 ? 1 : 0);
+  constexpr int TL = round_table_len(R);           // entries per table (16-byte multiple)
+  constexpr int NPF = ((TL - 2) / 2 + 63) / 64;    // 16-byte rounds chunks per lane
+  auto table = [&](int k) { return (const u32x4*)(a.rtab + ((size_t)k * 9 + cls) * TL); };
+  u32x4 pf[NPF], hdr;
+  auto prefetch = [&](int k) {
+    const u32x4* g = table(k);
+    hdr = g[0];
+#pragma unroll
+    for (int j = 0; j < NPF; ++j)
+      if (j * 64 + lane < (TL - 2) / 2) pf[j] = g[1 + j * 64 + lane];
+  };
+  auto park = [&]() {
+    u32x4* t4 = (u32x4*)L.tab;
+#pragma unroll
+    for (int j = 0; j < NPF; ++j)
+      if (j * 64 + lane < (TL - 2) / 2) t4[j * 64 + lane] = pf[j];
+  };
+  prefetch(0);
+  for (int k = 0; k < a.nsides; ++k) {
+    const int nrounds = (int)__builtin_amdgcn_readfirstlane(hdr.x);
+    park();
+    if (k + 1 < a.nsides) prefetch(k + 1);
+    __asm__ volatile("" ::: "memory");
+    dispatch_side<TX, TQ, R, SMAX, KAHAN>(a, c, xs, k, L.tab, nrounds);
+    __asm__ volatile("" ::: "memory");
+  }
   lds_store(c.consumed, npg);  // the last, partial page too
 
   for (int idx = lane; idx < fh * fw; idx += 64) {

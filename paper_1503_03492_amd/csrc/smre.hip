@@ -125,7 +125,65 @@ struct Plan {
   size_t qbytes = 0;
   size_t off_roff = 0, off_prev = 0, total = 0;
   std::vector<RegionStream> roff;  // page layout of each region's increments
+  // device metadata blob: the region streams, then (16-byte aligned) the round
+  // tables; meta_bytes covers both whether or not the blob is built
+  std::vector<unsigned char> meta;
+  size_t meta_rtab = 0, meta_bytes = 0;
 };
+
+// Footprint pitch of the sweep kernel instantiated for region side R (it
+// depends only on R and the largest side R + 1).
+int footprint_pitch(int R) {
+  switch (R) {
+    case 8: return PhaseShape<float, float, 8, 9>::P;
+    case 16: return PhaseShape<float, float, 16, 17>::P;
+    case 32: return PhaseShape<float, float, 32, 33>::P;
+    default: return 0;
+  }
+}
+
+// Round tables of one image (layout in kernels.hpp): for every side and
+// border class, the rounds of the region visiting order -- tiling offsets
+// (a', b') raster, then blocks of BR x BC windows of that offset -- with each
+// round's pixel offset in the footprint, its window counts and the end of its
+// increment bytes.  Border classes: regions in the last row / column of
+// regions (class 2) and the one before (class 1) may hold fewer anchors.
+void build_round_tables(const Plan& pl, int64_t H, int64_t W, size_t es, RoundEntry* out) {
+  const int R = pl.R, P = footprint_pitch(R), TL = round_table_len(R);
+  for (int k = 0; k < pl.nsides; ++k) {
+    const int S = pl.sides[k];
+    const Pattern pt = pattern(R, S);
+    for (int crow = 0; crow < 3; ++crow)
+      for (int ccol = 0; ccol < 3; ++ccol) {
+        auto extent = [&](int cls, int64_t n, int nreg) -> int {
+          const int64_t o = cls == 0 ? 0 : (int64_t)(nreg - (cls == 1 ? 2 : 1)) * R;
+          if (o < 0) return 0;
+          return (int)std::max<int64_t>(0, std::min<int64_t>(R, n - S + 1 - o));
+        };
+        const int rhi = extent(crow, H, pl.nry), chi = extent(ccol, W, pl.nrx);
+        RoundEntry* t = out + ((size_t)k * 9 + crow * 3 + ccol) * TL;
+        uint32_t cnt = 0, rb = 0;
+        for (int ap = 0; ap < std::min(S, rhi); ++ap) {
+          const int nr = (rhi - ap + S - 1) / S;
+          for (int bp = 0; bp < std::min(S, chi); ++bp) {
+            const int nc = (chi - bp + S - 1) / S;
+            for (int rby = 0; rby < nr; rby += pt.br) {
+              const int nbr = std::min(pt.br, nr - rby);
+              for (int rbx = 0; rbx < nc; rbx += pt.bc) {
+                const int nbc = std::min(pt.bc, nc - rbx);
+                const uint32_t xo = (uint32_t)((ap + S * rby) * P + (bp + S * rbx));
+                rb += (uint32_t)(nbr * nbc * S * S * (int)es);
+                t[2 + cnt] = RoundEntry{xo | ((uint32_t)nbc << 16) | ((uint32_t)nbr << 20), rb};
+                ++cnt;
+              }
+            }
+          }
+        }
+        t[0] = RoundEntry{cnt, 0};
+        t[1] = RoundEntry{0, 0};
+      }
+  }
+}
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -228,8 +286,16 @@ int plan_project(smre_dtype dt, int64_t H, int64_t W, const smre_params* p, Plan
   pl->nq = nq;
   pl->nwin = nwin;
   pl->qbytes = (size_t)(pages + 1) * kPage;
+  pl->meta_rtab = align_up((size_t)nreg * sizeof(RegionStream), 256);
+  pl->meta_bytes =
+      pl->meta_rtab + (size_t)pl->nsides * 9 * round_table_len(pl->R) * sizeof(RoundEntry);
+  if (need_offsets) {
+    pl->meta.assign(pl->meta_bytes, 0);
+    std::memcpy(pl->meta.data(), pl->roff.data(), (size_t)nreg * sizeof(RegionStream));
+    build_round_tables(*pl, H, W, es, (RoundEntry*)(pl->meta.data() + pl->meta_rtab));
+  }
   pl->off_roff = pl->qbytes;
-  pl->off_prev = align_up(pl->off_roff + (size_t)nreg * sizeof(RegionStream), 256);
+  pl->off_prev = align_up(pl->off_roff + pl->meta_bytes, 256);
   pl->total = align_up(pl->off_prev + (size_t)H * W * xs, 256);
   return SMRE_OK;
 }
@@ -335,12 +401,13 @@ int project_impl(smre_ctx* c, smre_dtype dt, void* x, int64_t H, int64_t W, int6
   const int64_t nwords = (int64_t)(pl.qbytes / 4);
   hipLaunchKernelGGL((fill_kernel<uint32_t>), dim3(grid_for(nwords)), dim3(256), 0, s,
                      (uint32_t*)ws, nwords, 0u);
-  HIP_OK(hipMemcpyAsync(ws + pl.off_roff, pl.roff.data(), pl.roff.size() * sizeof(RegionStream),
-                        hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(ws + pl.off_roff, pl.meta.data(), pl.meta.size(), hipMemcpyHostToDevice,
+                        s));
 
   ImageDesc a{};
   a.x = x;
   a.rs = (const RegionStream*)(ws + pl.off_roff);
+  a.rtab = (const RoundEntry*)(ws + pl.off_roff + pl.meta_rtab);
   a.ld = ld;
   a.q_byte = 0;
   a.H = (int)H;
@@ -519,7 +586,7 @@ struct BatchPlan {
   int n = 0;
   std::vector<Plan> plans;
   std::vector<size_t> qoff;       // byte offset of each image's increments
-  std::vector<size_t> roff_off;   // element offset of each image's region table
+  std::vector<size_t> roff_off;   // byte offset of each image's metadata blob
   std::vector<int64_t> prev_off;  // element offset of each image's snapshot
   size_t qbytes = 0, roff_elems = 0, prev_elems = 0;
   int nitems[4] = {0, 0, 0, 0};
@@ -557,7 +624,7 @@ int plan_batch(smre_dtype dt, int n, const smre_batch_image* im, const smre_batc
     B->qoff[i] = B->qbytes;
     B->qbytes += align_up(B->plans[i].qbytes, kPage);
     B->roff_off[i] = B->roff_elems;
-    B->roff_elems += (size_t)B->plans[i].nry * B->plans[i].nrx;
+    B->roff_elems += align_up(B->plans[i].meta_bytes, 256);
     B->prev_off[i] = (int64_t)B->prev_elems;
     B->prev_elems += (size_t)(im[i].H * im[i].W);
     const Plan& pl = B->plans[i];
@@ -566,7 +633,7 @@ int plan_batch(smre_dtype dt, int n, const smre_batch_image* im, const smre_batc
     items_total += (int64_t)pl.nry * pl.nrx;
   }
   B->off_roff = B->qbytes;
-  B->off_desc = align_up(B->off_roff + B->roff_elems * sizeof(RegionStream), 256);
+  B->off_desc = align_up(B->off_roff + B->roff_elems, 256);
   B->off_ctl = align_up(B->off_desc + sizeof(ImageDesc) * n, 256);
   B->off_items = align_up(B->off_ctl + sizeof(BatchCtl) * n, 256);
   B->off_cnt = align_up(B->off_items + sizeof(WorkItem) * items_total, 256);
@@ -671,7 +738,7 @@ int batch_setup(smre_ctx* c, smre_dtype dt, int n, const smre_batch_image* im,
   for (int c2 = 0; c2 < 4; ++c2) items_total += B.nitems[c2];
   host.assign(B.off_prev - B.off_roff, 0);
   unsigned char* h = host.data();
-  RegionStream* roff = (RegionStream*)(h + 0);
+  unsigned char* meta = h;
   ImageDesc* desc = (ImageDesc*)(h + (B.off_desc - B.off_roff));
   BatchCtl* ctl = (BatchCtl*)(h + (B.off_ctl - B.off_roff));
   WorkItem* items = (WorkItem*)(h + (B.off_items - B.off_roff));
@@ -682,10 +749,11 @@ int batch_setup(smre_ctx* c, smre_dtype dt, int n, const smre_batch_image* im,
   D->maxh = 1;
   for (int i = 0; i < n; ++i) {
     const Plan& pl = B.plans[i];
-    for (size_t k = 0; k < pl.roff.size(); ++k) roff[B.roff_off[i] + k] = pl.roff[k];
+    std::memcpy(meta + B.roff_off[i], pl.meta.data(), pl.meta.size());
     ImageDesc& a = desc[i];
     a.x = im[i].x;
-    a.rs = (const RegionStream*)(ws + B.off_roff) + B.roff_off[i];
+    a.rs = (const RegionStream*)(ws + B.off_roff + B.roff_off[i]);
+    a.rtab = (const RoundEntry*)(ws + B.off_roff + B.roff_off[i] + pl.meta_rtab);
     a.ld = im[i].ld;
     a.q_byte = (int64_t)B.qoff[i];
     a.H = (int)im[i].H;
@@ -1120,9 +1188,8 @@ class HipBackend : public smre_serve::Backend {
     HIP_OK(hipSetDevice(cfg_.device));
     HIP_OK(hipMemcpyAsync(base + off_x, r.in.data(), r.in.size() * sizeof(float),
                           hipMemcpyHostToDevice, stream_));
-    HIP_OK(hipMemcpyAsync(base + off_roff, sl.plan.roff.data(),
-                          sl.plan.roff.size() * sizeof(RegionStream), hipMemcpyHostToDevice,
-                          stream_));
+    HIP_OK(hipMemcpyAsync(base + off_roff, sl.plan.meta.data(), sl.plan.meta.size(),
+                          hipMemcpyHostToDevice, stream_));
     const int64_t nwords = (int64_t)(sl.plan.qbytes / 4);
     hipLaunchKernelGGL((fill_kernel<uint32_t>), dim3(grid_for(nwords)), dim3(256), 0, stream_,
                        (uint32_t*)base, nwords, 0u);
@@ -1131,6 +1198,7 @@ class HipBackend : public smre_serve::Backend {
     std::memset(&a, 0, sizeof a);
     a.x = base + off_x;
     a.rs = (const RegionStream*)(base + off_roff);
+    a.rtab = (const RoundEntry*)(base + off_roff + sl.plan.meta_rtab);
     a.ld = r.W;
     a.q_byte = (int64_t)at;
     a.H = r.H;
@@ -1267,7 +1335,7 @@ class HipBackend : public smre_serve::Backend {
   size_t layout(const Plan& pl, const smre_serve::Request& r, size_t* offs) const {
     size_t o = align_up(pl.qbytes, kPage);
     if (offs) offs[0] = o;
-    o = align_up(o + (size_t)pl.nry * pl.nrx * sizeof(RegionStream), 256);
+    o = align_up(o + pl.meta_bytes, 256);
     if (offs) offs[1] = o;
     o = align_up(o + (size_t)r.H * r.W * 4, 256);
     if (offs) offs[2] = o;
