@@ -413,10 +413,10 @@ __device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs
   const uint32_t qb0 = c.qb;
   uint32_t rb = 0;
   RoundEntry e = tab[0];
+  uint32_t rb_end = __builtin_amdgcn_readfirstlane(e.y);
   int i = 0;
   do {
     const RoundEntry en = tab[i + 1];  // entry past the last one is in the buffer, unused
-    const uint32_t rb_end = __builtin_amdgcn_readfirstlane(e.y);
     const uint32_t nbytes = rb_end - rb;
     int nbr = 1, nbc = 1;
     if constexpr (BR > 1) nbr = (int)((e.x >> 20) & 0xF);
@@ -535,6 +535,7 @@ __device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs
     lds_store(c.consumed, (int)((qb0 + rb_end) / kPage));
     rb = rb_end;
     e = en;
+    rb_end = __builtin_amdgcn_readfirstlane(en.y);  // read a round ago, long arrived
   } while (++i < nrounds);
   c.qb = qb0 + rb;
 }
