@@ -491,9 +491,17 @@ __device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs
         for (int v = 0; v < V; ++v) {
           const bool part_r = (u == U - 1) && (JRL < GR);
           const bool part_c = (v == V - 1) && (JCL < GC);
-          const int base = (part_r && part_c) ? bxw_rc : part_r ? bxw_r : part_c ? bxw_c : bxw;
           xn[u][v] = t * y[u][v];
-          xs[base + u * GR * P + v * GC] = xn[u][v];
+          if constexpr (BR == 1 && BC == 1) {
+            // one window per round: a masked element is a pixel outside the
+            // window that no other lane touches, so it gets its own value back
+            // (one base for all elements, so the writes pair up)
+            const bool keep = (part_r && part_c) ? (rl && cl) : part_r ? rl : part_c ? cl : true;
+            xs[bx + u * GR * P + v * GC] = keep ? xn[u][v] : xv[u][v];
+          } else {
+            const int base = (part_r && part_c) ? bxw_rc : part_r ? bxw_r : part_c ? bxw_c : bxw;
+            xs[base + u * GR * P + v * GC] = xn[u][v];
+          }
         }
 #pragma unroll
       for (int u = 0; u < U; ++u)
