@@ -412,11 +412,13 @@ __device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs
   // LDS, one entry per round (the next entry is read a round ahead).
   const uint32_t qb0 = c.qb;
   uint32_t rb = 0;
+  uint32_t ready_lim = (uint32_t)c.ready_seen * kPage - qb0;
   RoundEntry e = tab[0];
   uint32_t rb_end = __builtin_amdgcn_readfirstlane(e.y);
+  const RoundEntry* tn = tab + 1;
   int i = 0;
   do {
-    const RoundEntry en = tab[i + 1];  // entry past the last one is in the buffer, unused
+    const RoundEntry en = *tn++;  // entry past the last one is in the buffer, unused
     const uint32_t nbytes = rb_end - rb;
     int nbr = 1, nbc = 1;
     if constexpr (BR > 1) nbr = (int)((e.x >> 20) & 0xF);
@@ -424,9 +426,12 @@ __device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs
     // one-window blocks are always valid (a round holds at least one window)
     const bool valid = (BR == 1 || bry < nbr) && (BC == 1 || brx < nbc);
     const int woff = (bry * nbc + brx) * (S * S);
-    // wait until every page holding this round's bytes is in the ring
-    const int need = (int)((qb0 + rb_end + kPage - 1) / kPage);
-    if (__builtin_expect(need > c.ready_seen, 0)) c.ready_seen = wait_ge(c.ready, need, c.abort);
+    // wait until every page holding this round's bytes is in the ring (the
+    // bytes of the pages seen so far, relative to the side, bound the check)
+    if (__builtin_expect(rb_end > ready_lim, 0)) {
+      c.ready_seen = wait_ge(c.ready, (int)((qb0 + rb_end + kPage - 1) / kPage), c.abort);
+      ready_lim = (uint32_t)c.ready_seen * kPage - qb0;
+    }
     __asm__ volatile("" ::: "memory");
     const uint32_t roff = (qb0 + rb) & RMASK;
     // ring offsets of the lane's elements (full / last column slot); the
