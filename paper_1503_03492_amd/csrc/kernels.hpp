@@ -298,8 +298,9 @@ struct RegionStream {
 // One round of a side's visiting order in a region (see the round tables
 // below): x = pixel offset of the round's first window in the footprint (bits
 // 0..15) | windows of the round along a row of windows (bits 16..19) | along
-// a column (bits 20..23); y = end of the round's increment bytes, counted
-// from the side's first byte.
+// a column (bits 20..23), the counts left zero for sides whose rounds hold
+// one window; y = end of the round's increment bytes, counted from the side's
+// first byte.
 struct RoundEntry {
   uint32_t x, y;
 };
@@ -442,7 +443,7 @@ __device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs
     const uint32_t wfl = valid && cl ? ql : qdum;
     const uint32_t wlf = valid && rl ? qf : qdum;
     const uint32_t wll = valid && rl && cl ? ql : qdum;
-    const int bx = lane_x0 + (int)(e.x & 0xFFFF);
+    const int bx = lane_x0 + (int)((BR == 1 && BC == 1) ? e.x : (e.x & 0xFFFF));
     const int bxr = valid ? bx : 0;
     const int bxw = valid ? bx : xdum;
     const int bxw_r = valid && rl ? bx : xdum;

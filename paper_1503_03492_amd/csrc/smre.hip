@@ -173,7 +173,9 @@ void build_round_tables(const Plan& pl, int64_t H, int64_t W, size_t es, RoundEn
                 const int nbc = std::min(pt.bc, nc - rbx);
                 const uint32_t xo = (uint32_t)((ap + S * rby) * P + (bp + S * rbx));
                 rb += (uint32_t)(nbr * nbc * S * S * (int)es);
-                t[2 + cnt] = RoundEntry{xo | ((uint32_t)nbc << 16) | ((uint32_t)nbr << 20), rb};
+                const bool one = pt.br == 1 && pt.bc == 1;  // counts implied
+                t[2 + cnt] =
+                    RoundEntry{one ? xo : (xo | ((uint32_t)nbc << 16) | ((uint32_t)nbr << 20)), rb};
                 ++cnt;
               }
             }
