@@ -837,23 +837,43 @@ __global__ __launch_bounds__(256) void nonfinite_kernel(const TX* x, int64_t ld,
   if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&ctrl->nonfinite, 1);
 }
 
-// Feasibility: max over windows of side s of sum x^2 / r2 - 1, in FP64.
+// Feasibility: max over windows of side s of sum x^2 / r2 - 1, in FP64.  A
+// block takes a tile of VT x VW window anchors: it stages the squares of the
+// (VT + s - 1) x (VW + s - 1) pixels in LDS, sums each row over s columns,
+// then those row sums over s rows (O(s) adds per window instead of s^2 loads).
+constexpr int kViolTileH = 32, kViolTileW = 64, kViolMaxSide = 33;
 template <typename TX>
 __global__ __launch_bounds__(256) void violation_kernel(const TX* x, int64_t ld, int H, int W,
                                                         int s, double r2, Ctrl* ctrl) {
-  const int64_t nw = (int64_t)(H - s + 1) * (W - s + 1);
-  double m = -1.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t a = i / (W - s + 1), b = i - a * (W - s + 1);
-    double n = 0.0;
-    for (int r = 0; r < s; ++r) {
-      const TX* row = x + (a + r) * ld + b;
-      for (int cc = 0; cc < s; ++cc) {
-        const double v = (double)row[cc];
-        n = __builtin_fma(v, v, n);
-      }
+  constexpr int RT = kViolTileH + kViolMaxSide - 1, CT = kViolTileW + kViolMaxSide - 1;
+  __shared__ double sq[RT][CT];
+  __shared__ double hs[RT][kViolTileW];
+  const int a0 = blockIdx.y * kViolTileH, b0 = blockIdx.x * kViolTileW;
+  const int rows = kViolTileH + s - 1, cols = kViolTileW + s - 1;
+  for (int i = threadIdx.x; i < rows * cols; i += blockDim.x) {
+    const int r = i / cols, cc = i - (i / cols) * cols;
+    const int gr = a0 + r, gc = b0 + cc;
+    double v = 0.0;
+    if (gr < H && gc < W) {
+      v = (double)x[(int64_t)gr * ld + gc];
+      v = v * v;
     }
+    sq[r][cc] = v;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < rows * kViolTileW; i += blockDim.x) {
+    const int r = i / kViolTileW, cc = i - (i / kViolTileW) * kViolTileW;
+    double h = 0.0;
+    for (int j = 0; j < s; ++j) h += sq[r][cc + j];
+    hs[r][cc] = h;
+  }
+  __syncthreads();
+  double m = -1.0;
+  for (int i = threadIdx.x; i < kViolTileH * kViolTileW; i += blockDim.x) {
+    const int r = i / kViolTileW, cc = i - (i / kViolTileW) * kViolTileW;
+    if (a0 + r > H - s || b0 + cc > W - s) continue;  // window not fully inside
+    double n = 0.0;
+    for (int j = 0; j < s; ++j) n += hs[r + j][cc];
     m = fmax(m, n / r2 - 1.0);
   }
   m = block_max<TX>(m);

@@ -364,9 +364,11 @@ template <typename TX>
 int run_violation(smre_ctx* c, const void* x, int64_t H, int64_t W, int64_t ld, int n,
                   const int* sides, const double* r2, hipStream_t s, double* out) {
   for (int k = 0; k < n; ++k) {
-    const int64_t nw = (H - sides[k] + 1) * (W - sides[k] + 1);
-    hipLaunchKernelGGL((violation_kernel<TX>), dim3(grid_for(nw)), dim3(256), 0, s,
-                       (const TX*)x, ld, (int)H, (int)W, sides[k], r2[k], c->ctrl);
+    if (sides[k] > kViolMaxSide) return SMRE_EINVAL;
+    const dim3 grid((unsigned)((W - sides[k] + kViolTileW) / kViolTileW),
+                    (unsigned)((H - sides[k] + kViolTileH) / kViolTileH));
+    hipLaunchKernelGGL((violation_kernel<TX>), grid, dim3(256), 0, s, (const TX*)x, ld, (int)H,
+                       (int)W, sides[k], r2[k], c->ctrl);
   }
   HIP_OK(hipGetLastError());
   HIP_OK(hipMemcpyAsync(c->ctrl_host, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
@@ -1280,10 +1282,12 @@ class HipBackend : public smre_serve::Backend {
     double worst = 0.0;
     hipLaunchKernelGGL(ctrl_reset_kernel, dim3(1), dim3(1), 0, stream_, vctrl_);
     for (int k = 0; k < sl.plan.nsides; ++k) {
-      const int64_t nw = (int64_t)(r.H - sl.plan.sides[k] + 1) * (r.W - sl.plan.sides[k] + 1);
-      hipLaunchKernelGGL((violation_kernel<float>), dim3(grid_for(nw)), dim3(256), 0, stream_,
-                         (const float*)sl.desc.x, (int64_t)r.W, r.H, r.W, sl.plan.sides[k],
-                         sl.plan.r2[k], vctrl_);
+      const int sk = sl.plan.sides[k];
+      const dim3 grid((unsigned)((r.W - sk + kViolTileW) / kViolTileW),
+                      (unsigned)((r.H - sk + kViolTileH) / kViolTileH));
+      hipLaunchKernelGGL((violation_kernel<float>), grid, dim3(256), 0, stream_,
+                         (const float*)sl.desc.x, (int64_t)r.W, r.H, r.W, sk, sl.plan.r2[k],
+                         vctrl_);
     }
     HIP_OK(hipGetLastError());
     Ctrl vc;

@@ -264,6 +264,21 @@ def test_max_violation_matches_oracle(ctx):
     assert got == pytest.approx(oracle.max_violation(z, sides, r2), rel=1e-12, abs=1e-14)
 
 
+@pytest.mark.parametrize("side", [1, 5, 17, 31, 32])
+def test_max_violation_tiles_and_edges(ctx, side):
+    """Several 32 x 64 anchor tiles with ragged last tiles, each side alone (so
+    the reported maximum is that side's), FP64 and FP32 images."""
+    z = gi.emitters(150, 203, n_e=40, seed=11)
+    r2 = oracle.chi2_bounds([side])
+    want = oracle.max_violation(z, [side], r2)
+    got = ctx.max_violation(dev(z), [side], r2)
+    assert got == pytest.approx(want, rel=1e-12, abs=1e-14)
+    z32 = z.astype(np.float32)
+    want32 = oracle.max_violation(z32.astype(np.float64), [side], r2)
+    got32 = ctx.max_violation(dev(z32, torch.float32), [side], r2)
+    assert got32 == pytest.approx(want32, rel=1e-12, abs=1e-14)
+
+
 # ----------------------------------------------------------------- full size
 
 def test_config2_two_sweeps_match_oracle(ctx):
