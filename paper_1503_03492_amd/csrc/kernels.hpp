@@ -757,210 +757,4 @@ __global__ __launch_bounds__(128) void region_phase_batch(const ImageDesc* __res
   }
 }
 
-// ---------------------------------------------------------------- checks
-// Order-preserving map of doubles to unsigned 64-bit keys (for atomic max).
-__device__ __forceinline__ unsigned long long dkey(double d) {
-  unsigned long long u = (unsigned long long)__double_as_longlong(d);
-  return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
-}
-__host__ __device__ inline double dkey_inv(unsigned long long k) {
-  unsigned long long u = (k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k;
-  double d;
-  __builtin_memcpy(&d, &u, 8);
-  return d;
-}
-
-struct Ctrl {
-  int done;            // converged flag read by every sweep kernel
-  int done_sweep;      // sweep at which it converged
-  int nonfinite;       // input check result
-  int pad;
-  unsigned long long delta_key;  // running max |x - prev| of the checked sweep
-  double last_delta;
-  unsigned long long viol_key;   // running max violation
-};
-
-template <typename TX>
-__device__ __forceinline__ double block_max(double v) {
-  __shared__ double red[4];
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) red[w] = v;
-  __syncthreads();
-  v = red[0];
-  for (int i = 1; i < (int)(blockDim.x >> 6); ++i) v = fmax(v, red[i]);
-  return v;
-}
-
-// Image-wide passes: blocks stride over rows, threads over columns.
-template <typename TX>
-__global__ __launch_bounds__(256) void snapshot_kernel(const TX* x, int64_t ld, int H, int W,
-                                                       TX* prev, Ctrl* ctrl) {
-  if (ctrl->done) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->delta_key = dkey(0.0);
-  for (int r = blockIdx.x; r < H; r += gridDim.x)
-    for (int col = threadIdx.x; col < W; col += blockDim.x)
-      prev[(int64_t)r * W + col] = x[(int64_t)r * ld + col];
-}
-
-template <typename TX>
-__global__ __launch_bounds__(256) void delta_kernel(const TX* x, int64_t ld, int H, int W,
-                                                    const TX* prev, Ctrl* ctrl) {
-  if (ctrl->done) return;
-  double m = 0.0;
-  for (int r = blockIdx.x; r < H; r += gridDim.x)
-    for (int col = threadIdx.x; col < W; col += blockDim.x)
-      m = fmax(m, fabs((double)x[(int64_t)r * ld + col] - (double)prev[(int64_t)r * W + col]));
-  m = block_max<TX>(m);
-  if (threadIdx.x == 0) atomicMax(&ctrl->delta_key, dkey(m));
-}
-
-__global__ void decide_kernel(Ctrl* ctrl, double tol, int sweep) {
-  if (ctrl->done) return;
-  const double d = dkey_inv(ctrl->delta_key);
-  ctrl->last_delta = d;
-  if (d < tol) {
-    ctrl->done = 1;
-    ctrl->done_sweep = sweep;
-  }
-}
-
-template <typename TX>
-__global__ __launch_bounds__(256) void nonfinite_kernel(const TX* x, int64_t ld, int H, int W,
-                                                        Ctrl* ctrl) {
-  int bad = 0;
-  for (int r = blockIdx.x; r < H; r += gridDim.x)
-    for (int col = threadIdx.x; col < W; col += blockDim.x) {
-      const double v = (double)x[(int64_t)r * ld + col];
-      bad |= !(v - v == 0.0);
-    }
-  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&ctrl->nonfinite, 1);
-}
-
-// Feasibility: max over windows of side s of sum x^2 / r2 - 1, in FP64.  A
-// block takes a tile of VT x VW window anchors: it stages the squares of the
-// (VT + s - 1) x (VW + s - 1) pixels in LDS, sums each row over s columns,
-// then those row sums over s rows (O(s) adds per window instead of s^2 loads).
-constexpr int kViolTileH = 32, kViolTileW = 64, kViolMaxSide = 33;
-template <typename TX>
-__global__ __launch_bounds__(256) void violation_kernel(const TX* x, int64_t ld, int H, int W,
-                                                        int s, double r2, Ctrl* ctrl) {
-  constexpr int RT = kViolTileH + kViolMaxSide - 1, CT = kViolTileW + kViolMaxSide - 1;
-  __shared__ double sq[RT][CT];
-  __shared__ double hs[RT][kViolTileW];
-  const int a0 = blockIdx.y * kViolTileH, b0 = blockIdx.x * kViolTileW;
-  const int rows = kViolTileH + s - 1, cols = kViolTileW + s - 1;
-  for (int i = threadIdx.x; i < rows * cols; i += blockDim.x) {
-    const int r = i / cols, cc = i - (i / cols) * cols;
-    const int gr = a0 + r, gc = b0 + cc;
-    double v = 0.0;
-    if (gr < H && gc < W) {
-      v = (double)x[(int64_t)gr * ld + gc];
-      v = v * v;
-    }
-    sq[r][cc] = v;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < rows * kViolTileW; i += blockDim.x) {
-    const int r = i / kViolTileW, cc = i - (i / kViolTileW) * kViolTileW;
-    double h = 0.0;
-    for (int j = 0; j < s; ++j) h += sq[r][cc + j];
-    hs[r][cc] = h;
-  }
-  __syncthreads();
-  double m = -1.0;
-  for (int i = threadIdx.x; i < kViolTileH * kViolTileW; i += blockDim.x) {
-    const int r = i / kViolTileW, cc = i - (i / kViolTileW) * kViolTileW;
-    if (a0 + r > H - s || b0 + cc > W - s) continue;  // window not fully inside
-    double n = 0.0;
-    for (int j = 0; j < s; ++j) n += hs[r + j][cc];
-    m = fmax(m, n / r2 - 1.0);
-  }
-  m = block_max<TX>(m);
-  if (threadIdx.x == 0) atomicMax(&ctrl->viol_key, dkey(m));
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void fill_kernel(T* p, int64_t n, T v) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = v;
-}
-
-__global__ void ctrl_reset_kernel(Ctrl* c) {
-  c->done = 0;
-  c->done_sweep = 0;
-  c->nonfinite = 0;
-  c->delta_key = dkey(0.0);
-  c->last_delta = -1.0;
-  c->viol_key = dkey(-1.0);
-}
-
-// ---------------------------------------------------------------- batch control
-template <typename TX>
-__global__ __launch_bounds__(256) void snapshot_batch(const ImageDesc* __restrict__ imgs,
-                                                      BatchCtl* ctl, TX* prev) {
-  const int im = blockIdx.y;
-  if (ctl[im].done || (ctl[im].sweeps + 1) % ctl[im].check_every != 0) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctl[im].delta_key = dkey(0.0);
-  const ImageDesc& a = imgs[im];
-  const TX* x = (const TX*)a.x;
-  TX* pv = prev + ctl[im].prev_off;
-  for (int r = blockIdx.x; r < a.H; r += gridDim.x)
-    for (int col = threadIdx.x; col < a.W; col += blockDim.x)
-      pv[(int64_t)r * a.W + col] = x[(int64_t)r * a.ld + col];
-}
-
-template <typename TX>
-__global__ __launch_bounds__(256) void delta_batch(const ImageDesc* __restrict__ imgs,
-                                                   BatchCtl* ctl, const TX* prev) {
-  const int im = blockIdx.y;
-  if (ctl[im].done || (ctl[im].sweeps + 1) % ctl[im].check_every != 0) return;
-  const ImageDesc& a = imgs[im];
-  const TX* x = (const TX*)a.x;
-  const TX* pv = prev + ctl[im].prev_off;
-  double m = 0.0;
-  for (int r = blockIdx.x; r < a.H; r += gridDim.x)
-    for (int col = threadIdx.x; col < a.W; col += blockDim.x)
-      m = fmax(m, fabs((double)x[(int64_t)r * a.ld + col] - (double)pv[(int64_t)r * a.W + col]));
-  m = block_max<TX>(m);
-  if (threadIdx.x == 0) atomicMax(&ctl[im].delta_key, dkey(m));
-}
-
-// One block: close the sweep for every image (check and/or sweep cap) and
-// count the images still running.  counters[0] = sweeps done, [1] = active.
-__global__ __launch_bounds__(256) void decide_batch(BatchCtl* ctl, int n, int check,
-                                                    int* counters) {
-  __shared__ int active;
-  const int sweep = counters[0] + 1;
-  if (threadIdx.x == 0) active = 0;
-  __syncthreads();
-  for (int im = threadIdx.x; im < n; im += blockDim.x) {
-    BatchCtl& c = ctl[im];
-    if (c.done) continue;
-    const int sw = ++c.sweeps;
-    bool stop = false;
-    if (check && sw % c.check_every == 0) {
-      const double d = dkey_inv(c.delta_key);
-      c.last_delta = d;
-      if (d < c.tol) {
-        c.converged = 1;
-        stop = true;
-      }
-    }
-    if (sw >= c.max_sweeps) stop = true;
-    if (stop) {
-      c.done = 1;
-      c.done_sweep = sw;
-    } else {
-      atomicAdd(&active, 1);
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    counters[0] = sweep;
-    counters[1] = active;
-  }
-}
-
 }  // namespace smre

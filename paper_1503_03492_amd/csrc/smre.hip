@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "icd.hpp"
+#include "checks.hpp"
 #include "kernels.hpp"
 #include "serve_core.hpp"
 #include "smre.h"
