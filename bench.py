@@ -444,7 +444,9 @@ def main():
                      "kernel": "region_phase",
                      "copy_gbs_measured": copy_gbs,
                      "frac_of_copy": achieved / copy_gbs if achieved and copy_gbs else None,
-                     "bytes_per_launch": bytes_alg / launches if launches else None},
+                     # per working launch: four colour launches per sweep on this image
+                     # (launches queued past convergence exit at once and move nothing)
+                     "bytes_per_launch": bytes_alg / (4 * sum(sweeps)) if sweeps else None},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x0.astype(np.float64), sides, r2)
