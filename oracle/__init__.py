@@ -51,6 +51,15 @@ def lib():
                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, dp,
                                  ctypes.POINTER(ctypes.c_int64)]
         L.oracle_icd.restype = ctypes.c_int
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        L.oracle_philox4x64_10.argtypes = [u64p, u64p, u64p]
+        L.oracle_philox4x64_10.restype = None
+        L.oracle_mc_field.argtypes = [ctypes.c_uint64, i64, i64, i64, dp]
+        L.oracle_mc_field.restype = None
+        L.oracle_mc_statistic.argtypes = [dp, i64, i64, ip, ctypes.c_int32, dp]
+        L.oracle_mc_statistic.restype = ctypes.c_double
+        L.oracle_order_quantile.argtypes = [dp, i64, ctypes.c_double]
+        L.oracle_order_quantile.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -161,3 +170,40 @@ def icd(x0, K, r2, tol=1e-13, mode=TOL_MAXABS, max_inner=100000, num_phases=None
     if rc != 0:
         raise ValueError("oracle_icd rejected its arguments")
     return z, tot.value
+
+
+# ---------------------------------------------------------------- Monte-Carlo weights
+
+def philox4x64_10(ctr, key):
+    """One Philox4x64-10 block: 4 counter words, 2 key words -> 4 words."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    lib().oracle_philox4x64_10(c.ctypes.data_as(u64p), k.ctypes.data_as(u64p),
+                               out.ctypes.data_as(u64p))
+    return out
+
+
+def mc_field(seed, f, H, W):
+    """Field f (H x W) of the Monte-Carlo sample drawn with `seed`."""
+    out = np.empty((H, W), dtype=np.float64)
+    lib().oracle_mc_field(int(seed), int(f), int(H), int(W), _d(out))
+    return out
+
+
+def mc_statistic(e, sides):
+    """(Q, tmax) of one field: Q = max over windows of ((t)^(1/4) - mu_s) / sigma_s,
+    tmax[k] = largest window sum of squares of side sides[k]."""
+    e = np.ascontiguousarray(e, dtype=np.float64)
+    sides = np.ascontiguousarray(sides, dtype=np.int32)
+    tmax = np.empty(len(sides), dtype=np.float64)
+    q = lib().oracle_mc_statistic(_d(e), e.shape[0], e.shape[1], _i(sides), len(sides),
+                                  _d(tmax))
+    return q, tmax
+
+
+def order_quantile(q, alpha):
+    """ceil(alpha n)-th smallest of the samples q."""
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    return lib().oracle_order_quantile(_d(q), len(q), float(alpha))

@@ -498,3 +498,124 @@ int oracle_icd(const double* x0, int64_t H, int64_t W, int32_t K, const double* 
   free(ybuf);
   return 0;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Monte-Carlo weights (Sec. 2.1)                                              */
+/* ------------------------------------------------------------------------- */
+
+/* The paper balances the window bounds through q_alpha, the alpha-quantile of
+ *   Q = max over windows S of ((t_S)^(1/4) - mu_s) / sigma_s,  t_S = sum_S e^2,
+ * for a field e of i.i.d. N(0,1) values, with mu_s = (|S| - 1/2)^(1/4) and
+ * sigma_s^2 = 1/(8 sqrt|S|).  The paper does not say how the fields are drawn;
+ * here they come from a counter-based generator so that any field can be
+ * recomputed on its own:
+ *   Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+ *   easy as 1, 2, 3", SC 2011): a 4 x 64-bit counter block is mixed by ten
+ *   rounds; each round multiplies words 0 and 2 by fixed odd constants, takes
+ *   the 128-bit products apart and recombines them with words 1 and 3 and the
+ *   key; the key is advanced by two Weyl constants between rounds.
+ *   Pixel p = i W + j of field f is normal number (p mod 4) of the block with
+ *   counter {p / 4, f, 0, 0} and key {seed, 0}; the words (w0, w1) and (w2, w3)
+ *   become two normals each by the Box-Muller transform with
+ *   u = ((w >> 11) + 1/2) 2^-53. */
+
+#define PHILOX_M0 0xD2E7470EE14C6C93ULL
+#define PHILOX_M1 0xCA5A826395121157ULL
+#define PHILOX_W0 0x9E3779B97F4A7C15ULL
+#define PHILOX_W1 0xBB67AE8584CAA73BULL
+
+void oracle_philox4x64_10(const uint64_t* ctr, const uint64_t* key, uint64_t* out) {
+  uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint64_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0 && ORACLE_MUTANT != 6) {
+      k0 += PHILOX_W0;
+      k1 += PHILOX_W1;
+    }
+    unsigned __int128 p0 = (unsigned __int128)PHILOX_M0 * c0;
+    unsigned __int128 p1 = (unsigned __int128)PHILOX_M1 * c2;
+    uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+    uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+    uint64_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+    c0 = n0;
+    c1 = n1;
+    c2 = n2;
+    c3 = n3;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+static double unit_open(uint64_t w) { return ((double)(w >> 11) + 0.5) * 0x1p-53; }
+
+/* Field f (H x W, row-major) of the Monte-Carlo sample. */
+void oracle_mc_field(uint64_t seed, int64_t f, int64_t H, int64_t W, double* out) {
+  const double two_pi = 6.283185307179586;
+  for (int64_t p = 0; p < H * W; ++p) {
+    uint64_t ctr[4] = {(uint64_t)(p / 4), (uint64_t)f, 0, 0}, key[2] = {seed, 0}, w[4];
+    oracle_philox4x64_10(ctr, key, w);
+    int lane = (int)(p % 4);
+    double u0 = unit_open(w[lane < 2 ? 0 : 2]);
+    double u1 = unit_open(w[lane < 2 ? 1 : 3]);
+#if ORACLE_MUTANT == 9
+    double r = sqrt(-log(u0));
+#else
+    double r = sqrt(-2.0 * log(u0));
+#endif
+    out[p] = (lane % 2 == 0) ? r * cos(two_pi * u1) : r * sin(two_pi * u1);
+  }
+}
+
+/* Q of one field, from the definition: every window S of every listed side,
+ * t_S summed directly, transformed and maximised.  tmax_out[k] (may be NULL)
+ * receives max_S t_S over the windows of side sides[k] (-1 if none fits). */
+double oracle_mc_statistic(const double* e, int64_t H, int64_t W, const int32_t* sides,
+                           int32_t nsides, double* tmax_out) {
+  double Q = -INFINITY;
+  for (int k = 0; k < nsides; ++k) {
+    const int32_t s = sides[k];
+    const double npix = (double)s * (double)s;
+#if ORACLE_MUTANT == 5
+    const double mu = pow(npix, 0.25);
+#else
+    const double mu = pow(npix - 0.5, 0.25);
+#endif
+    const double sigma = sqrt(1.0 / (8.0 * sqrt(npix)));
+    double tmax = -1.0;
+    for (int64_t i0 = 0; i0 + s <= H; ++i0)
+      for (int64_t j0 = 0; j0 + s <= W; ++j0) {
+        double t = 0.0;
+        for (int64_t i = i0; i < i0 + s; ++i)
+          for (int64_t j = j0; j < j0 + s - (ORACLE_MUTANT == 7); ++j) t += e[i * W + j] * e[i * W + j];
+        if (t > tmax) tmax = t;
+        double v = (pow(t, 0.25) - mu) / sigma;
+        if (v > Q) Q = v;
+      }
+    if (tmax_out) tmax_out[k] = tmax;
+  }
+  return Q;
+}
+
+static int cmp_double(const void* a, const void* b) {
+  double x = *(const double*)a, y = *(const double*)b;
+  return (x > y) - (x < y);
+}
+
+/* Empirical alpha-quantile of n samples: the smallest sample q with at least
+ * ceil(alpha n) samples <= q, i.e. the ceil(alpha n)-th order statistic
+ * (0 < alpha <= 1).  Returns NaN for invalid arguments. */
+double oracle_order_quantile(const double* q, int64_t n, double alpha) {
+  if (n < 1 || !(alpha > 0.0) || alpha > 1.0) return NAN;
+  double* v = (double*)malloc((size_t)n * sizeof(double));
+  if (!v) return NAN;
+  memcpy(v, q, (size_t)n * sizeof(double));
+  qsort(v, (size_t)n, sizeof(double), cmp_double);
+  int64_t k = (int64_t)ceil(alpha * (double)n);
+  if (k < 1) k = 1;
+  if (k > n) k = n;
+  double r = v[ORACLE_MUTANT == 8 && k < n ? k : k - 1];
+  free(v);
+  return r;
+}
