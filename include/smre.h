@@ -247,6 +247,49 @@ int smre_max_violation(smre_ctx* ctx, smre_dtype dtype, const void* x, int64_t H
                        int64_t ld, int32_t n_sides, const int32_t* sides, const double* radius2,
                        void* stream, double* out);
 
+/* ---- Monte-Carlo weights (Sec. 2.1, selection of the weights) ----
+ * The paper balances the window bounds with q_alpha, the alpha-quantile of
+ *   Q = max over windows S of ((t_S)^(1/4) - mu_s) / sigma_s,  t_S = sum_S e^2,
+ * where e is an H x W field of i.i.d. N(0,1) values, mu_s = (s^2 - 1/2)^(1/4)
+ * and sigma_s^2 = 1/(8 s); the bounds are then r2_s = (q_alpha sigma_s + mu_s)^4
+ * (smre_paper_bounds).  These calls estimate q_alpha by sampling fields; the
+ * family is every s x s window inside the field, for each listed side
+ * (1 <= s <= min(H, W), s <= 32, distinct, at most 32 sides).
+ *
+ * Drawn fields: pixel p = i W + j (row-major) of field f is normal number
+ * (p mod 4) of the Philox4x64-10 block (Salmon, Moraes, Dror, Shaw, SC 2011)
+ * with counter {p / 4, f, 0, 0} and key {seed, 0}; words (w0, w1) and (w2, w3)
+ * give two normals each by Box-Muller: u = ((w >> 11) + 1/2) 2^-53,
+ * z = sqrt(-2 ln u0) cos(2 pi u1), z' = sqrt(-2 ln u0) sin(2 pi u1).
+ * Sums, transform and maximum are FP64.  H, W <= 2^20.  Results go to HOST
+ * arrays; each call returns when they are written. */
+
+/* Fields field0 .. field0 + n_fields - 1 to out (device, FP64): field k at
+ * out + k H ld, row stride ld >= W. */
+int smre_mc_fields(smre_ctx* ctx, int64_t H, int64_t W, uint64_t seed, int64_t field0,
+                   int64_t n_fields, double* out, int64_t ld, void* stream);
+
+/* Q of the drawn fields field0 .. field0 + n_fields - 1: q_out[n_fields]
+ * (host).  tmax_out (host, may be NULL): [n_fields][n_sides], the largest
+ * window sum of squares of each side, sides in the caller's order.  report
+ * (may be NULL): elapsed_ms, kernel_ms / kernel_launches of the window kernels
+ * (when timing is on), window_projections = windows evaluated. */
+int smre_mc_statistic(smre_ctx* ctx, int64_t H, int64_t W, int32_t n_sides, const int32_t* sides,
+                      uint64_t seed, int64_t field0, int64_t n_fields, double* q_out,
+                      double* tmax_out, void* stream, smre_report* report);
+
+/* As smre_mc_statistic, for caller-supplied fields (device, dtype FP32 or
+ * FP64): field k at fields + k H ld elements, row stride ld >= W. */
+int smre_mc_statistic_fields(smre_ctx* ctx, smre_dtype dtype, const void* fields, int64_t H,
+                             int64_t W, int64_t ld, int64_t n_fields, int32_t n_sides,
+                             const int32_t* sides, double* q_out, double* tmax_out, void* stream);
+
+/* q_alpha from fields 0 .. n_fields - 1: the ceil(alpha n_fields)-th smallest
+ * Q (0 < alpha <= 1).  report as in smre_mc_statistic. */
+int smre_mc_quantile(smre_ctx* ctx, int64_t H, int64_t W, int32_t n_sides, const int32_t* sides,
+                     uint64_t seed, int64_t n_fields, double alpha, double* q_alpha, void* stream,
+                     smre_report* report);
+
 #ifdef __cplusplus
 }
 #endif

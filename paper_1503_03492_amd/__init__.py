@@ -113,6 +113,14 @@ def _load():
                                   ctypes.c_size_t, ctypes.POINTER(Report),
                                   ctypes.POINTER(ctypes.c_double)]
     L.smre_serve_stats.argtypes = [vp, ctypes.POINTER(ServeCounters)]
+    u64 = ctypes.c_uint64
+    L.smre_mc_fields.argtypes = [vp, i64, i64, u64, i64, i64, vp, i64, vp]
+    L.smre_mc_statistic.argtypes = [vp, i64, i64, i32, ip, u64, i64, i64, dp, dp, vp,
+                                    ctypes.POINTER(Report)]
+    L.smre_mc_statistic_fields.argtypes = [vp, ctypes.c_int, vp, i64, i64, i64, i64, i32, ip, dp,
+                                           dp, vp]
+    L.smre_mc_quantile.argtypes = [vp, i64, i64, i32, ip, u64, i64, dbl, dp, vp,
+                                   ctypes.POINTER(Report)]
     return L
 
 
@@ -122,7 +130,8 @@ EXPORTS = ["smre_status_string", "smre_ctx_create", "smre_ctx_destroy", "smre_ct
            "smre_chi2_bounds", "smre_paper_bounds", "smre_workspace_size",
            "smre_dykstra_project", "smre_dykstra_incomplete", "smre_max_violation",
            "smre_batch_workspace_size", "smre_dykstra_project_batch", "smre_serve_create",
-           "smre_serve_destroy", "smre_serve_submit", "smre_serve_poll", "smre_serve_stats"]
+           "smre_serve_destroy", "smre_serve_submit", "smre_serve_poll", "smre_serve_stats",
+           "smre_mc_fields", "smre_mc_statistic", "smre_mc_statistic_fields", "smre_mc_quantile"]
 
 
 def lib():
@@ -320,6 +329,61 @@ class Context:
                                        W, ld, len(s), sp, rp, _stream(stream), ctypes.byref(out)),
                "smre_max_violation")
         return out.value
+
+    # ---- Monte-Carlo weights (the paper's q_alpha) ----
+    def mc_fields(self, out, seed, field0=0, stream=None):
+        """Write drawn fields field0 .. field0 + n - 1 into out, a float64 CUDA
+        tensor of shape (n, H, W) with unit column stride."""
+        import torch
+        if not isinstance(out, torch.Tensor) or not out.is_cuda or out.dtype != torch.float64:
+            raise TypeError("out must be a float64 CUDA tensor")
+        if out.dim() != 3 or out.stride(2) != 1 or out.stride(0) != out.shape[1] * out.stride(1):
+            raise ValueError("out must be (n, H, W) with fields stacked at stride H * ld")
+        n, H, W = out.shape
+        _check(_lib.smre_mc_fields(self._h, H, W, int(seed), int(field0), n,
+                                   ctypes.c_void_p(out.data_ptr()), out.stride(1),
+                                   _stream(stream)), "smre_mc_fields")
+
+    def mc_statistic(self, H, W, sides, seed, n_fields, field0=0, want_tmax=False, stream=None):
+        """Q of drawn fields (numpy array); with want_tmax also the largest
+        window sum of squares per (field, side)."""
+        s, sp = _ivec(sides)
+        q = np.empty(int(n_fields))
+        t = np.empty((int(n_fields), len(s))) if want_tmax else None
+        rep = Report()
+        _check(_lib.smre_mc_statistic(self._h, int(H), int(W), len(s), sp, int(seed), int(field0),
+                                      int(n_fields), _dvec(q)[1],
+                                      _dvec(t)[1] if t is not None else None, _stream(stream),
+                                      ctypes.byref(rep)), "smre_mc_statistic")
+        return (q, t, rep.as_dict()) if want_tmax else (q, rep.as_dict())
+
+    def mc_statistic_fields(self, fields, sides, stream=None):
+        """(Q, tmax) of caller-supplied fields: a (n, H, W) CUDA tensor."""
+        import torch
+        if not isinstance(fields, torch.Tensor) or not fields.is_cuda or fields.dim() != 3:
+            raise TypeError("fields must be an (n, H, W) CUDA tensor")
+        if fields.stride(2) != 1 or fields.stride(0) != fields.shape[1] * fields.stride(1):
+            raise ValueError("fields must be stacked at stride H * ld with unit column stride")
+        n, H, W = fields.shape
+        s, sp = _ivec(sides)
+        q = np.empty(n)
+        t = np.empty((n, len(s)))
+        _check(_lib.smre_mc_statistic_fields(self._h, _dtype_code(fields),
+                                             ctypes.c_void_p(fields.data_ptr()), H, W,
+                                             fields.stride(1), n, len(s), sp, _dvec(q)[1],
+                                             _dvec(t)[1], _stream(stream)),
+               "smre_mc_statistic_fields")
+        return q, t
+
+    def mc_quantile(self, H, W, sides, seed, n_fields, alpha, stream=None):
+        """(q_alpha, report) from fields 0 .. n_fields - 1."""
+        s, sp = _ivec(sides)
+        q = ctypes.c_double()
+        rep = Report()
+        _check(_lib.smre_mc_quantile(self._h, int(H), int(W), len(s), sp, int(seed),
+                                     int(n_fields), float(alpha), ctypes.byref(q),
+                                     _stream(stream), ctypes.byref(rep)), "smre_mc_quantile")
+        return q.value, rep.as_dict()
 
 
 class Server:

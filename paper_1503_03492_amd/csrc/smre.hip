@@ -24,6 +24,7 @@
 #include "icd.hpp"
 #include "checks.hpp"
 #include "kernels.hpp"
+#include "mc.hpp"
 #include "serve_core.hpp"
 #include "smre.h"
 
@@ -61,6 +62,8 @@ struct smre_ctx {
   hipStream_t capture = nullptr;     // private stream for graph capture
   std::map<std::string, int> tuned;  // autotuned region side per batch key
   int cus = 0;
+  unsigned long long* mc_tmax = nullptr;  // Monte-Carlo per-(field, side) maxima
+  double* mc_q = nullptr;                 // Monte-Carlo statistic per field
 };
 
 namespace {
@@ -1454,6 +1457,118 @@ double chi2_quantile(int k, double p) {
   return x;
 }
 
+// ---------------------------------------------------------------- Monte-Carlo weights
+constexpr int kMcChunk = 4096;  // fields per tile launch
+
+int mc_sides(int32_t n, const int32_t* sides, int64_t H, int64_t W, McSides* sd) {
+  if (!sides || n < 1 || n > kMcMaxSide) return SMRE_EINVAL;
+  std::memset(sd, 0, sizeof(*sd));
+  for (int s = 0; s <= kMcMaxSide; ++s) sd->slot[s] = -1;
+  for (int k = 0; k < n; ++k) {
+    const int s = sides[k];
+    if (s < 1 || s > kMcMaxSide || s > H || s > W || sd->slot[s] >= 0) return SMRE_EINVAL;
+    sd->slot[s] = k;
+    sd->side[k] = s;
+    sd->smax = std::max(sd->smax, s);
+  }
+  sd->n = n;
+  return SMRE_OK;
+}
+
+int mc_check_shape(int64_t H, int64_t W, int64_t n_fields) {
+  if (H < 1 || W < 1 || H > (1 << 20) || W > (1 << 20) || n_fields < 1) return SMRE_EINVAL;
+  return SMRE_OK;
+}
+
+int mc_buffers(smre_ctx* c) {
+  if (!c->mc_tmax) {
+    HIP_OK(hipMalloc(&c->mc_tmax, sizeof(unsigned long long) * kMcChunk * kMcMaxSide));
+    HIP_OK(hipMalloc(&c->mc_q, sizeof(double) * kMcChunk));
+  }
+  return SMRE_OK;
+}
+
+template <bool GEN, typename T, int SMAX>
+void mc_tiles(const T* fields, int64_t fstride, int64_t ld, int H, int W, uint64_t seed,
+              int64_t f0, int nf, const McSides& sd, unsigned long long* tmax, hipStream_t s) {
+  constexpr int TR = mc_tile_rows(SMAX);
+  const dim3 grid((unsigned)((W + kMcTileW - 1) / kMcTileW), (unsigned)((H + TR - 1) / TR),
+                  (unsigned)nf);
+  hipLaunchKernelGGL((mc_window_max<GEN, T, SMAX>), grid, dim3(256), 0, s, fields, fstride, ld, H,
+                     W, seed, f0, sd, tmax);
+}
+
+// Q (and optionally the per-side maxima) of fields f0 .. f0 + nf - 1, drawn
+// (GEN) or read from `fields`; results to host arrays.
+template <bool GEN, typename T>
+int mc_run(smre_ctx* c, const T* fields, int64_t ld, int64_t H, int64_t W, uint64_t seed,
+           int64_t f0, int64_t nf, const McSides& sd, double* q_out, double* tmax_out,
+           hipStream_t s, TimingAcc& acc) {
+  int rc = mc_buffers(c);
+  if (rc) return rc;
+  const int64_t fstride = H * ld;
+  for (int64_t done = 0; done < nf; done += kMcChunk) {
+    const int m = (int)std::min<int64_t>(kMcChunk, nf - done);
+    hipLaunchKernelGGL((fill_kernel<unsigned long long>), dim3(grid_for((int64_t)m * sd.n)),
+                       dim3(256), 0, s, c->mc_tmax, (int64_t)m * sd.n, 0ull);
+    int slot;
+    rc = timing_begin(c, acc, s, &slot);
+    if (rc) return rc;
+    const T* fp = GEN ? fields : fields + done * fstride;
+    if (sd.smax <= 8)
+      mc_tiles<GEN, T, 8>(fp, fstride, ld, (int)H, (int)W, seed, f0 + done, m, sd, c->mc_tmax, s);
+    else if (sd.smax <= 16)
+      mc_tiles<GEN, T, 16>(fp, fstride, ld, (int)H, (int)W, seed, f0 + done, m, sd, c->mc_tmax, s);
+    else
+      mc_tiles<GEN, T, 32>(fp, fstride, ld, (int)H, (int)W, seed, f0 + done, m, sd, c->mc_tmax, s);
+    HIP_OK(hipGetLastError());
+    rc = timing_end(c, acc, s, slot);
+    if (rc) return rc;
+    hipLaunchKernelGGL(mc_q_kernel, dim3((m + 255) / 256), dim3(256), 0, s, c->mc_tmax, m, sd,
+                       c->mc_q);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(q_out + done, c->mc_q, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+    if (tmax_out)
+      HIP_OK(hipMemcpyAsync(tmax_out + done * sd.n, c->mc_tmax,
+                            sizeof(double) * (size_t)m * sd.n, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));  // the buffers are reused by the next chunk
+  }
+  return timing_flush(c, acc, true);
+}
+
+void mc_report(smre_report* rep, const TimingAcc& acc, float ms, int64_t H, int64_t W,
+               int64_t nf, const McSides& sd, double bytes) {
+  if (!rep) return;
+  std::memset(rep, 0, sizeof(*rep));
+  double windows = 0.0;
+  for (int k = 0; k < sd.n; ++k)
+    windows += (double)(H - sd.side[k] + 1) * (double)(W - sd.side[k] + 1);
+  rep->sweeps = 0;
+  rep->converged = 1;
+  rep->last_delta = NAN;
+  rep->max_violation = NAN;
+  rep->elapsed_ms = ms;
+  rep->kernel_ms = acc.ms;
+  rep->kernel_launches = acc.launches;
+  rep->bytes_moved = bytes;
+  rep->window_projections = windows * (double)nf;
+}
+
+int mc_statistic_gen(smre_ctx* c, int64_t H, int64_t W, const McSides& sd, uint64_t seed,
+                     int64_t f0, int64_t nf, double* q_out, double* tmax_out, hipStream_t s,
+                     smre_report* rep) {
+  HIP_OK(hipEventRecord(c->t0, s));
+  TimingAcc acc;
+  int rc = mc_run<true, double>(c, nullptr, W, H, W, seed, f0, nf, sd, q_out, tmax_out, s, acc);
+  if (rc) return rc;
+  HIP_OK(hipEventRecord(c->t1, s));
+  HIP_OK(hipEventSynchronize(c->t1));
+  float ms = 0.f;
+  HIP_OK(hipEventElapsedTime(&ms, c->t0, c->t1));
+  mc_report(rep, acc, ms, H, W, nf, sd, 0.0);
+  return SMRE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1507,6 +1622,8 @@ void smre_ctx_destroy(smre_ctx* c) {
   if (c->t1) (void)hipEventDestroy(c->t1);
   if (c->counters_host) (void)hipHostFree(c->counters_host);
   if (c->capture) (void)hipStreamDestroy(c->capture);
+  if (c->mc_tmax) (void)hipFree(c->mc_tmax);
+  if (c->mc_q) (void)hipFree(c->mc_q);
   delete c;
 }
 
@@ -1658,6 +1775,86 @@ int smre_max_violation(smre_ctx* c, smre_dtype dt, const void* x, int64_t H, int
   if (dt == SMRE_F64) return run_violation<double>(c, x, H, W, ld, n, sides, r2, s, out);
   if (dt == SMRE_F32) return run_violation<float>(c, x, H, W, ld, n, sides, r2, s, out);
   return SMRE_EINVAL;
+}
+
+int smre_mc_fields(smre_ctx* c, int64_t H, int64_t W, uint64_t seed, int64_t field0,
+                   int64_t n_fields, double* out, int64_t ld, void* stream) {
+  if (!c || !out || field0 < 0 || ld < W) return SMRE_EINVAL;
+  int rc = mc_check_shape(H, W, n_fields);
+  if (rc) return rc;
+  rc = set_device(c);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t groups = (H * W + 3) / 4;
+  const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, (groups + 255) / 256));
+  for (int64_t done = 0; done < n_fields; done += 65535) {
+    const unsigned m = (unsigned)std::min<int64_t>(65535, n_fields - done);
+    hipLaunchKernelGGL(mc_fields_kernel, dim3(gx, m), dim3(256), 0, s, out + done * H * ld, H * ld,
+                       ld, (int)H, (int)W, seed, field0 + done);
+    HIP_OK(hipGetLastError());
+  }
+  HIP_OK(hipStreamSynchronize(s));
+  return SMRE_OK;
+}
+
+int smre_mc_statistic(smre_ctx* c, int64_t H, int64_t W, int32_t n_sides, const int32_t* sides,
+                      uint64_t seed, int64_t field0, int64_t n_fields, double* q_out,
+                      double* tmax_out, void* stream, smre_report* report) {
+  if (!c || !q_out || field0 < 0) return SMRE_EINVAL;
+  int rc = mc_check_shape(H, W, n_fields);
+  if (rc) return rc;
+  McSides sd;
+  rc = mc_sides(n_sides, sides, H, W, &sd);
+  if (rc) return rc;
+  rc = set_device(c);
+  if (rc) return rc;
+  return mc_statistic_gen(c, H, W, sd, seed, field0, n_fields, q_out, tmax_out,
+                          (hipStream_t)stream, report);
+}
+
+int smre_mc_statistic_fields(smre_ctx* c, smre_dtype dt, const void* fields, int64_t H, int64_t W,
+                             int64_t ld, int64_t n_fields, int32_t n_sides, const int32_t* sides,
+                             double* q_out, double* tmax_out, void* stream) {
+  if (!c || !fields || !q_out || ld < W) return SMRE_EINVAL;
+  int rc = mc_check_shape(H, W, n_fields);
+  if (rc) return rc;
+  McSides sd;
+  rc = mc_sides(n_sides, sides, H, W, &sd);
+  if (rc) return rc;
+  rc = set_device(c);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  TimingAcc acc;
+  if (dt == SMRE_F64)
+    return mc_run<false, double>(c, (const double*)fields, ld, H, W, 0, 0, n_fields, sd, q_out,
+                                 tmax_out, s, acc);
+  if (dt == SMRE_F32)
+    return mc_run<false, float>(c, (const float*)fields, ld, H, W, 0, 0, n_fields, sd, q_out,
+                                tmax_out, s, acc);
+  return SMRE_EINVAL;
+}
+
+int smre_mc_quantile(smre_ctx* c, int64_t H, int64_t W, int32_t n_sides, const int32_t* sides,
+                     uint64_t seed, int64_t n_fields, double alpha, double* q_alpha, void* stream,
+                     smre_report* report) {
+  if (!c || !q_alpha || !(alpha > 0.0) || alpha > 1.0) return SMRE_EINVAL;
+  int rc = mc_check_shape(H, W, n_fields);
+  if (rc) return rc;
+  McSides sd;
+  rc = mc_sides(n_sides, sides, H, W, &sd);
+  if (rc) return rc;
+  rc = set_device(c);
+  if (rc) return rc;
+  std::vector<double> q((size_t)n_fields);
+  rc = mc_statistic_gen(c, H, W, sd, seed, 0, n_fields, q.data(), nullptr, (hipStream_t)stream,
+                        report);
+  if (rc) return rc;
+  // the ceil(alpha n)-th smallest sample
+  int64_t k = (int64_t)std::ceil(alpha * (double)n_fields);
+  k = std::min<int64_t>(std::max<int64_t>(k, 1), n_fields);
+  std::nth_element(q.begin(), q.begin() + (k - 1), q.end());
+  *q_alpha = q[(size_t)(k - 1)];
+  return SMRE_OK;
 }
 
 struct smre_server {
