@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6  # MI355X vector FP64 (256 CUs x 2.4 GHz x 64 lanes x 2 per FMA)
 KERNEL_SRC = os.path.join(ROOT, "paper_1503_03492_amd", "csrc", "kernels.hpp")
 
 
@@ -264,6 +265,77 @@ def bench_icd(args):
     print(json.dumps(out), flush=True)
 
 
+def mc_flops_per_field(H, W, sides):
+    """FP64 operations one field needs in the running-sum evaluation the
+    window kernel performs: a square per pixel, one add per pixel for each
+    side up to the largest (row sums grow by a column), and per window two
+    adds (sliding column sum) and one compare (running maximum)."""
+    smax = max(sides)
+    windows = sum((H - s + 1) * (W - s + 1) for s in sides)
+    return H * W * (1 + smax) + 3 * windows
+
+
+def bench_mc(args):
+    """The paper's weights (Sec. 2.1): Monte-Carlo estimate of q_alpha, the
+    0.9-quantile of the max statistic Q over all windows of sides 1..16 of
+    1024^2 N(0,1) fields drawn on the GPU (Philox4x64-10 + Box-Muller)."""
+    import torch
+
+    import paper_1503_03492_amd as smre
+    H = W = 1024
+    sides = list(range(1, 17))
+    n, alpha = args.mc_fields, 0.9
+    ctx = smre.Context(0)
+    ctx.set_timing(True)
+    for i in range(args.warmup):
+        ctx.mc_quantile(H, W, sides, 1000 + i, min(n, 256), alpha)
+    torch.cuda.synchronize()
+    reps, qs = [], []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        q, rep = ctx.mc_quantile(H, W, sides, k, n, alpha)
+        qs.append(q)
+        reps.append(rep)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kms = sum(r["kernel_ms"] for r in reps)
+    launches = sum(r["kernel_launches"] for r in reps)
+    fpf = mc_flops_per_field(H, W, sides)
+    fields = n * args.steps
+    achieved = fpf * fields / (kms * 1e-3) / 1e12 if kms else None
+    out = {"metric": "Monte-Carlo fields/s (q_alpha of the max window statistic, 1024^2 fields)",
+           "value": fields / el, "unit": "fields/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (fields drawn on the GPU)",
+           "config": {"workload": "mc_qalpha_1024sq_sides1-16", "H": H, "W": W,
+                      "sides": "1..16", "fields_per_step": n, "alpha": alpha},
+           "q_alpha": qs, "window_sums_per_s": sum(r["window_projections"] for r in reps) / el,
+           "kernel_us_per_field": kms * 1e3 / fields,
+           "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS if achieved
+                        else None, "traffic": None, "kernel": "mc_window_max",
+                        "flops_per_field": fpf,
+                        "kernel_avg_us": kms / launches * 1e3 if launches else None}}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_mc(H, W, sides)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_mc(H, W, sides, budget_s=12.0):
+    """The oracle, as it is, on whole fields of the same workload until about
+    budget_s have elapsed (one thread)."""
+    import oracle
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < budget_s:
+        oracle.mc_statistic(oracle.mc_field(7, n, H, W), sides)
+        n += 1
+    el = time.perf_counter() - t0
+    return {"value": n / el, "unit": "fields/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} whole {H}x{W} fields, sides 1..{max(sides)}, {el:.1f} s"}
+
+
 def bench_full_vs_icd(args):
     """512^2 emitter image (200 emitters): full Dykstra (sides 1..8, FP32, tol
     1e-5) against the paper's incomplete Dykstra (K = 3: squares of side 1, 2,
@@ -323,6 +395,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c3")
+    ap.add_argument("--mc-fields", type=int, default=4096,
+                    help="mc workload: fields per quantile estimate (one step)")
     ap.add_argument("--region", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-n", type=int, default=64)
@@ -350,6 +424,8 @@ def main():
         return bench_icd(args)
     if args.workload == "fullvsicd":
         return bench_full_vs_icd(args)
+    if args.workload == "mc":
+        return bench_mc(args)
 
     import torch
 
