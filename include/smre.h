@@ -108,6 +108,8 @@ typedef struct {
   double bytes_moved;          /* algorithmic HBM bytes of the sweeps           */
   double window_projections;   /* single-window projections performed           */
   int64_t kernel_launches;     /* sweep-kernel launches timed                   */
+  double pixel_updates;        /* (window, pixel) pairs updated: the sum of the
+                                  pixel counts of the projections performed     */
 } smre_report;
 
 const char* smre_status_string(int status);
@@ -152,6 +154,19 @@ int smre_dykstra_incomplete(smre_ctx* ctx, smre_dtype dtype, void* x, int64_t H,
                             int64_t ld, int32_t K, const double* radius2, double tol,
                             int32_t tolmode, int32_t max_inner, int32_t num_phases, void* stream,
                             smre_report* report);
+
+/* The incomplete Dykstra on every frame of a movie (the paper preprocesses the
+ * frames of a fluorescence time series with it, Sec. 4): frames of H x W (row
+ * stride ld) stacked
+ * H ld elements apart from x (device), each projected in place exactly as
+ * smre_dykstra_incomplete would project it alone; every phase is one launch
+ * over all frames.  frames * H <= 2^31 - 1.  report: inner_sweeps, window and
+ * pixel counts summed over frames; max_violation over all frames. */
+int smre_dykstra_incomplete_frames(smre_ctx* ctx, smre_dtype dtype, void* x, int64_t H,
+                                   int64_t W, int64_t ld, int64_t frames, int32_t K,
+                                   const double* radius2, double tol, int32_t tolmode,
+                                   int32_t max_inner, int32_t num_phases, void* stream,
+                                   smre_report* report);
 
 /* ---- Batches: images of different sizes in one persistent launch per colour ----
  * Each image carries its own sides, bounds, tolerance and sweep cap; the

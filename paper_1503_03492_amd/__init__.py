@@ -42,7 +42,7 @@ class Report(ctypes.Structure):
                 ("last_delta", ctypes.c_double), ("max_violation", ctypes.c_double),
                 ("elapsed_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double),
                 ("bytes_moved", ctypes.c_double), ("window_projections", ctypes.c_double),
-                ("kernel_launches", ctypes.c_int64)]
+                ("kernel_launches", ctypes.c_int64), ("pixel_updates", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -97,6 +97,9 @@ def _load():
                                        ctypes.POINTER(Report)]
     L.smre_dykstra_incomplete.argtypes = [vp, ctypes.c_int, vp, i64, i64, i64, i32, dp, dbl,
                                           i32, i32, i32, vp, ctypes.POINTER(Report)]
+    L.smre_dykstra_incomplete_frames.argtypes = [vp, ctypes.c_int, vp, i64, i64, i64, i64, i32,
+                                                 dp, dbl, i32, i32, i32, vp,
+                                                 ctypes.POINTER(Report)]
     L.smre_max_violation.argtypes = [vp, ctypes.c_int, vp, i64, i64, i64, i32, ip, dp, vp, dp]
     L.smre_batch_workspace_size.argtypes = [ctypes.c_int, i32, ctypes.POINTER(BatchImage),
                                             ctypes.POINTER(BatchParams),
@@ -128,7 +131,8 @@ _lib = _load()
 
 EXPORTS = ["smre_status_string", "smre_ctx_create", "smre_ctx_destroy", "smre_ctx_set_timing",
            "smre_chi2_bounds", "smre_paper_bounds", "smre_workspace_size",
-           "smre_dykstra_project", "smre_dykstra_incomplete", "smre_max_violation",
+           "smre_dykstra_project", "smre_dykstra_incomplete", "smre_dykstra_incomplete_frames",
+           "smre_max_violation",
            "smre_batch_workspace_size", "smre_dykstra_project_batch", "smre_serve_create",
            "smre_serve_destroy", "smre_serve_submit", "smre_serve_poll", "smre_serve_stats",
            "smre_mc_fields", "smre_mc_statistic", "smre_mc_statistic_fields", "smre_mc_quantile"]
@@ -283,6 +287,30 @@ class Context:
                                           int(max_inner), int(num_phases), _stream(stream),
                                           ctypes.byref(rep))
         _check(rc, "smre_dykstra_incomplete")
+        return rep.as_dict()
+
+    def incomplete_frames(self, x, K, radius2, tol=1e-3, mode=TOL_MEANABS, max_inner=10000,
+                          num_phases=None, stream=None):
+        """Incomplete Dykstra of every frame of x, an (n, H, W) CUDA tensor with
+        frames stacked at stride H * ld, in place; returns the report dict."""
+        import torch
+        if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dim() != 3:
+            raise TypeError("x must be an (n, H, W) CUDA tensor")
+        if x.stride(2) != 1 or x.stride(0) != x.shape[1] * x.stride(1):
+            raise ValueError("frames must be stacked at stride H * ld with unit column stride")
+        n, H, W = x.shape
+        r, rp = _dvec(radius2)
+        if len(r) != K + 1:
+            raise ValueError("radius2 needs K+1 entries")
+        if num_phases is None:
+            num_phases = K + 1
+        rep = Report()
+        rc = _lib.smre_dykstra_incomplete_frames(self._h, _dtype_code(x),
+                                                 ctypes.c_void_p(x.data_ptr()), H, W, x.stride(1),
+                                                 n, int(K), rp, float(tol), int(mode),
+                                                 int(max_inner), int(num_phases), _stream(stream),
+                                                 ctypes.byref(rep))
+        _check(rc, "smre_dykstra_incomplete_frames")
         return rep.as_dict()
 
     def project_batch(self, xs, sides, radius2, tol=1e-5, max_sweeps=5000, region=0,

@@ -92,10 +92,13 @@ __global__ __launch_bounds__(256) void nonfinite_kernel(const TX* x, int64_t ld,
 // block takes a tile of VT x VW window anchors: it stages the squares of the
 // (VT + s - 1) x (VW + s - 1) pixels in LDS, sums each row over s columns,
 // then those row sums over s rows (O(s) adds per window instead of s^2 loads).
+// blockIdx.z selects a frame of a movie (frames fstride elements apart).
 constexpr int kViolTileH = 32, kViolTileW = 64, kViolMaxSide = 33;
 template <typename TX>
-__global__ __launch_bounds__(256) void violation_kernel(const TX* x, int64_t ld, int H, int W,
-                                                        int s, double r2, Ctrl* ctrl) {
+__global__ __launch_bounds__(256) void violation_kernel(const TX* x, int64_t fstride, int64_t ld,
+                                                        int H, int W, int s, double r2,
+                                                        Ctrl* ctrl) {
+  x += (int64_t)blockIdx.z * fstride;
   constexpr int RT = kViolTileH + kViolMaxSide - 1, CT = kViolTileW + kViolMaxSide - 1;
   __shared__ double sq[RT][CT];
   __shared__ double hs[RT][kViolTileW];
@@ -128,7 +131,13 @@ __global__ __launch_bounds__(256) void violation_kernel(const TX* x, int64_t ld,
     m = fmax(m, n / r2 - 1.0);
   }
   m = block_max<TX>(m);
-  if (threadIdx.x == 0) atomicMax(&ctrl->viol_key, dkey(m));
+  if (threadIdx.x == 0) {
+    // skip the atomic when the running maximum is already at least m (a stale
+    // read only costs an unneeded atomic): over many frames most blocks do
+    const unsigned long long k = dkey(m);
+    if (k > __hip_atomic_load(&ctrl->viol_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(&ctrl->viol_key, k);
+  }
 }
 
 template <typename T>

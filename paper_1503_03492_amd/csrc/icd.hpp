@@ -7,6 +7,9 @@
 // zeroed at the phase start, until the block converges.  Blocks of a phase
 // are disjoint, so one wave per block runs them all in parallel.
 //
+// A movie of frames (same size, stacked at a fixed stride) runs in the same
+// launches: blockIdx.z selects the frame, so every phase covers all frames.
+//
 // Layout inside a wave: the block's 4^K pixels in Morton (Z) order, NPL =
 // max(1, 4^K / 64) consecutive Morton indices per lane.  A square of side 2^k
 // is then an aligned run of 4^k Morton indices: inside one lane when
@@ -39,7 +42,8 @@ template <typename T> __device__ __forceinline__ T wave_max(T v) {
 }
 
 struct IcdArgs {
-  void* x;
+  void* x;            // frame 0; frame f at x + f * fstride elements
+  int64_t fstride;
   int64_t ld;
   int32_t H, W;
   int32_t phase;
@@ -48,9 +52,13 @@ struct IcdArgs {
   int32_t pad;
   double tol;
   double r2[6];
-  int* inner_count;   // total inner sweeps (device)
-  unsigned long long* proj_count;  // total square projections (device)
+  // Work counters (device): kIcdSlots slots of kIcdSlotWords words, one
+  // 128-byte line each; a block adds its inner sweeps, square projections
+  // and (square, pixel) updates to words 0, 1, 2 of slot (block id mod
+  // kIcdSlots), so no line takes more than a share of the blocks' atomics.
+  unsigned long long* counters;
 };
+constexpr int kIcdSlots = 256, kIcdSlotWords = 16;
 
 template <typename T, int K>
 __global__ __launch_bounds__(64) void icd_phase(IcdArgs a) {
@@ -62,7 +70,7 @@ __global__ __launch_bounds__(64) void icd_phase(IcdArgs a) {
   const int o = (1 << i) & (B - 1);
   const int by = (o > 0 ? o - B : 0) + (int)blockIdx.y * B;
   const int bx = (o > 0 ? o - B : 0) + (int)blockIdx.x * B;
-  T* xg = (T*)a.x;
+  T* xg = (T*)a.x + (int64_t)blockIdx.z * a.fstride;
 
   T x[NPL];
   bool inimg[NPL];
@@ -103,6 +111,14 @@ __global__ __launch_bounds__(64) void icd_phase(IcdArgs a) {
       leaders += (k >= i && active[k][e] && ((lane * NPL + e) & ((1 << (2 * k)) - 1)) == 0);
   float nsq = (float)leaders;
   nsq = group_sum<64>(nsq);
+  // (square, pixel) pairs updated per inner sweep
+  int upix = 0;
+#pragma unroll
+  for (int k = 0; k <= K; ++k)
+#pragma unroll
+    for (int e = 0; e < NPL; ++e) upix += (k >= i && active[k][e]);
+  float nunit = (float)upix;
+  nunit = group_sum<64>(nunit);
 
   T q[K + 1][NPL];
 #pragma unroll
@@ -180,8 +196,11 @@ __global__ __launch_bounds__(64) void icd_phase(IcdArgs a) {
   for (int e = 0; e < NPL; ++e)
     if (inimg[e]) xg[(int64_t)gy[e] * a.ld + gx[e]] = x[e];
   if (lane == 0) {
-    atomicAdd(a.inner_count, it);
-    atomicAdd(a.proj_count, (unsigned long long)it * (unsigned long long)(nsq + 0.5f));
+    const unsigned blk = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    unsigned long long* c = a.counters + (blk % kIcdSlots) * kIcdSlotWords;
+    atomicAdd(c + 0, (unsigned long long)it);
+    atomicAdd(c + 1, (unsigned long long)it * (unsigned long long)(nsq + 0.5f));
+    atomicAdd(c + 2, (unsigned long long)it * (unsigned long long)(nunit + 0.5f));
   }
 }
 

@@ -112,7 +112,7 @@ __global__ __launch_bounds__(256) void mc_fields_kernel(double* __restrict__ out
   }
 }
 
-__device__ __forceinline__ double wave_max(double v) {
+__device__ __forceinline__ double mc_wave_max(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(256) void mc_window_max(const T* __restrict__ field
             if (j + 1 < RPL) n = (n + h[j + s]) - h[j];
           }
         }
-        m = wave_max(m);
+        m = mc_wave_max(m);
         if (c == 0) red[s - 1][wv] = m;
       }
     }

@@ -62,6 +62,7 @@ struct smre_ctx {
   hipStream_t capture = nullptr;     // private stream for graph capture
   std::map<std::string, int> tuned;  // autotuned region side per batch key
   int cus = 0;
+  unsigned long long* icd_cnt = nullptr;  // ICD work counters (kIcdSlots lines)
   unsigned long long* mc_tmax = nullptr;  // Monte-Carlo per-(field, side) maxima
   double* mc_q = nullptr;                 // Monte-Carlo statistic per field
 };
@@ -366,13 +367,18 @@ int launch_phase_any(smre_dtype dt, int inc, int kahan, int R, const ImageDesc& 
 
 template <typename TX>
 int run_violation(smre_ctx* c, const void* x, int64_t H, int64_t W, int64_t ld, int n,
-                  const int* sides, const double* r2, hipStream_t s, double* out) {
-  for (int k = 0; k < n; ++k) {
-    if (sides[k] > kViolMaxSide) return SMRE_EINVAL;
-    const dim3 grid((unsigned)((W - sides[k] + kViolTileW) / kViolTileW),
-                    (unsigned)((H - sides[k] + kViolTileH) / kViolTileH));
-    hipLaunchKernelGGL((violation_kernel<TX>), grid, dim3(256), 0, s, (const TX*)x, ld, (int)H,
-                       (int)W, sides[k], r2[k], c->ctrl);
+                  const int* sides, const double* r2, hipStream_t s, double* out,
+                  int64_t frames = 1) {
+  for (int64_t f0 = 0; f0 < frames; f0 += 65535) {
+    const unsigned nz = (unsigned)std::min<int64_t>(65535, frames - f0);
+    const TX* xf = (const TX*)x + f0 * H * ld;
+    for (int k = 0; k < n; ++k) {
+      if (sides[k] > kViolMaxSide) return SMRE_EINVAL;
+      const dim3 grid((unsigned)((W - sides[k] + kViolTileW) / kViolTileW),
+                      (unsigned)((H - sides[k] + kViolTileH) / kViolTileH), nz);
+      hipLaunchKernelGGL((violation_kernel<TX>), grid, dim3(256), 0, s, xf, H * ld, ld, (int)H,
+                         (int)W, sides[k], r2[k], c->ctrl);
+    }
   }
   HIP_OK(hipGetLastError());
   HIP_OK(hipMemcpyAsync(c->ctrl_host, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
@@ -505,32 +511,43 @@ int project_impl(smre_ctx* c, smre_dtype dt, void* x, int64_t H, int64_t W, int6
     rep->kernel_launches = tacc.launches;
     rep->bytes_moved = (double)sweeps_run * (2.0 * es * (double)pl.nq + 2.0 * sizeof(TX) * (double)H * W);
     rep->window_projections = (double)sweeps_run * (double)pl.nwin;
+    rep->pixel_updates = (double)sweeps_run * (double)pl.nq;
   }
   if (checking && !fin.done) return SMRE_NOT_CONVERGED;
   return SMRE_OK;
 }
 
+template <bool GEN, typename T>
+int mc_run(smre_ctx* c, const T* fields, int64_t ld, int64_t H, int64_t W, uint64_t seed,
+           int64_t f0, int64_t nf, const McSides& sd, double* q_out, double* tmax_out,
+           hipStream_t s, TimingAcc& acc);
+int mc_sides(int32_t n, const int32_t* sides, int64_t H, int64_t W, McSides* sd);
+
 template <typename T>
-int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int K, const double* r2,
-             double tol, int mode, int max_inner, int nph, hipStream_t s, smre_report* rep) {
+int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t frames, int K,
+             const double* r2, double tol, int mode, int max_inner, int nph, hipStream_t s,
+             smre_report* rep) {
   HIP_OK(hipEventRecord(c->t0, s));
   hipLaunchKernelGGL(ctrl_reset_kernel, dim3(1), dim3(1), 0, s, c->ctrl);
   bool bad = false;
-  int rc = check_nonfinite<T>(c, x, H, W, ld, s, &bad);
+  // frames are stacked H * ld elements apart: one tall image of frames * H rows
+  int rc = check_nonfinite<T>(c, x, frames * H, W, ld, s, &bad);
   if (rc) return rc;
   if (bad) return SMRE_ENONFINITE;
-  hipLaunchKernelGGL((fill_kernel<int>), dim3(1), dim3(64), 0, s, c->counter, (int64_t)4, 0);
+  constexpr int64_t kCntWords = (int64_t)kIcdSlots * kIcdSlotWords;
+  if (!c->icd_cnt) HIP_OK(hipMalloc(&c->icd_cnt, sizeof(unsigned long long) * kCntWords));
+  hipLaunchKernelGGL((fill_kernel<unsigned long long>), dim3(grid_for(kCntWords)), dim3(256), 0,
+                     s, c->icd_cnt, kCntWords, 0ull);
   IcdArgs a{};
-  a.x = x;
   a.ld = ld;
+  a.fstride = H * ld;
   a.H = (int)H;
   a.W = (int)W;
   a.mode = mode;
   a.max_inner = max_inner;
   a.tol = tol;
   for (int k = 0; k <= K; ++k) a.r2[k] = r2[k];
-  a.inner_count = c->counter;
-  a.proj_count = (unsigned long long*)(c->counter + 2);
+  a.counters = c->icd_cnt;
   const int B = 1 << K;
   TimingAcc tacc;
   for (int ph = 0; ph < nph; ++ph) {
@@ -541,33 +558,54 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int K, cons
     int slot;
     rc = timing_begin(c, tacc, s, &slot);
     if (rc) return rc;
-    switch (K) {
-      case 0: hipLaunchKernelGGL((icd_phase<T, 0>), dim3(nbx, nby), dim3(64), 0, s, a); break;
-      case 1: hipLaunchKernelGGL((icd_phase<T, 1>), dim3(nbx, nby), dim3(64), 0, s, a); break;
-      case 2: hipLaunchKernelGGL((icd_phase<T, 2>), dim3(nbx, nby), dim3(64), 0, s, a); break;
-      case 3: hipLaunchKernelGGL((icd_phase<T, 3>), dim3(nbx, nby), dim3(64), 0, s, a); break;
-      case 4: hipLaunchKernelGGL((icd_phase<T, 4>), dim3(nbx, nby), dim3(64), 0, s, a); break;
-      default: hipLaunchKernelGGL((icd_phase<T, 5>), dim3(nbx, nby), dim3(64), 0, s, a); break;
+    for (int64_t f0 = 0; f0 < frames; f0 += 65535) {
+      const dim3 grid(nbx, nby, (unsigned)std::min<int64_t>(65535, frames - f0));
+      a.x = (T*)x + f0 * H * ld;
+      switch (K) {
+        case 0: hipLaunchKernelGGL((icd_phase<T, 0>), grid, dim3(64), 0, s, a); break;
+        case 1: hipLaunchKernelGGL((icd_phase<T, 1>), grid, dim3(64), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((icd_phase<T, 2>), grid, dim3(64), 0, s, a); break;
+        case 3: hipLaunchKernelGGL((icd_phase<T, 3>), grid, dim3(64), 0, s, a); break;
+        case 4: hipLaunchKernelGGL((icd_phase<T, 4>), grid, dim3(64), 0, s, a); break;
+        default: hipLaunchKernelGGL((icd_phase<T, 5>), grid, dim3(64), 0, s, a); break;
+      }
+      HIP_OK(hipGetLastError());
     }
-    HIP_OK(hipGetLastError());
     rc = timing_end(c, tacc, s, slot);
     if (rc) return rc;
   }
   HIP_OK(hipStreamSynchronize(s));
   rc = timing_flush(c, tacc, true);
   if (rc) return rc;
-  int cnt[4] = {0, 0, 0, 0};
-  HIP_OK(hipMemcpy(cnt, c->counter, sizeof(cnt), hipMemcpyDeviceToHost));
-  const int inner = cnt[0];
-  unsigned long long proj = 0;
-  std::memcpy(&proj, cnt + 2, sizeof proj);
-  std::vector<int> sides(K + 1);
-  for (int k = 0; k <= K; ++k) sides[k] = 1 << k;
-  double viol = 0.0;
+  std::vector<unsigned long long> slots((size_t)kCntWords);
+  HIP_OK(hipMemcpy(slots.data(), c->icd_cnt, sizeof(unsigned long long) * kCntWords,
+                   hipMemcpyDeviceToHost));
+  unsigned long long cnt[3] = {0, 0, 0};
+  for (int k = 0; k < kIcdSlots; ++k)
+    for (int w = 0; w < 3; ++w) cnt[w] += slots[(size_t)k * kIcdSlotWords + w];
   // Reported: the violation over the FULL family of the levels' sides (every
-  // position), i.e. how far ICD is from feasibility for the exact method.
-  rc = run_violation<T>(c, x, H, W, ld, K + 1, sides.data(), r2, s, &viol);
+  // position, every frame), i.e. how far ICD is from feasibility for the
+  // exact method: the largest window sum of each (frame, side) from the
+  // all-sides tile kernel, then the worst ratio to its bound.
+  std::vector<int32_t> fam;
+  std::vector<double> fam_r2;
+  for (int k = 0; k <= K; ++k)
+    if ((1 << k) <= H && (1 << k) <= W) {
+      fam.push_back(1 << k);
+      fam_r2.push_back(r2[k]);
+    }
+  McSides sd;
+  rc = mc_sides((int32_t)fam.size(), fam.data(), H, W, &sd);
   if (rc) return rc;
+  std::vector<double> qf((size_t)frames), tmax((size_t)frames * fam.size());
+  TimingAcc vacc;
+  rc = mc_run<false, T>(c, (const T*)x, ld, H, W, 0, 0, frames, sd, qf.data(), tmax.data(), s,
+                        vacc);
+  if (rc) return rc;
+  double viol = -INFINITY;
+  for (int64_t f = 0; f < frames; ++f)
+    for (size_t k = 0; k < fam.size(); ++k)
+      viol = std::max(viol, tmax[(size_t)f * fam.size() + k] / fam_r2[k] - 1.0);
   HIP_OK(hipEventRecord(c->t1, s));
   HIP_OK(hipEventSynchronize(c->t1));
   float ms = 0.f;
@@ -576,14 +614,15 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int K, cons
     rep->sweeps = nph;
     rep->converged = 1;
     rep->region = B;
-    rep->inner_sweeps = inner;
+    rep->inner_sweeps = (int32_t)std::min<unsigned long long>(cnt[0], INT32_MAX);
     rep->last_delta = NAN;
     rep->max_violation = viol;
     rep->elapsed_ms = ms;
     rep->kernel_ms = tacc.ms;
     rep->kernel_launches = tacc.launches;
-    rep->bytes_moved = 2.0 * sizeof(T) * (double)H * W * nph;
-    rep->window_projections = (double)proj;
+    rep->bytes_moved = 2.0 * sizeof(T) * (double)H * W * nph * (double)frames;
+    rep->window_projections = (double)cnt[1];
+    rep->pixel_updates = (double)cnt[2];
   }
   return SMRE_OK;
 }
@@ -1020,6 +1059,7 @@ int batch_impl(smre_ctx* c, smre_dtype dt, int n, const smre_batch_image* im,
       r.kernel_launches = tacc.launches;
       r.bytes_moved = (double)sw * (2.0 * es * (double)pl.nq + 2.0 * sizeof(TX) * (double)(im[i].H * im[i].W));
       r.window_projections = (double)sw * (double)pl.nwin;
+      r.pixel_updates = (double)sw * (double)pl.nq;
     }
   }
   return all_conv ? SMRE_OK : SMRE_NOT_CONVERGED;
@@ -1290,8 +1330,8 @@ class HipBackend : public smre_serve::Backend {
       const dim3 grid((unsigned)((r.W - sk + kViolTileW) / kViolTileW),
                       (unsigned)((r.H - sk + kViolTileH) / kViolTileH));
       hipLaunchKernelGGL((violation_kernel<float>), grid, dim3(256), 0, stream_,
-                         (const float*)sl.desc.x, (int64_t)r.W, r.H, r.W, sk, sl.plan.r2[k],
-                         vctrl_);
+                         (const float*)sl.desc.x, (int64_t)0, (int64_t)r.W, r.H, r.W, sk,
+                         sl.plan.r2[k], vctrl_);
     }
     HIP_OK(hipGetLastError());
     Ctrl vc;
@@ -1304,6 +1344,7 @@ class HipBackend : public smre_serve::Backend {
                         (2.0 * (cfg_.inc == SMRE_INC_BF16 ? 2 : 4) * (double)sl.plan.nq +
                          8.0 * (double)r.H * r.W);
     r.rep.window_projections = (double)sl.last.done_sweep * (double)sl.plan.nwin;
+    r.rep.pixel_updates = (double)sl.last.done_sweep * (double)sl.plan.nq;
     free_.release(sl.off, sl.size);
     sl.active = false;
     dirty_ = true;
@@ -1622,6 +1663,7 @@ void smre_ctx_destroy(smre_ctx* c) {
   if (c->t1) (void)hipEventDestroy(c->t1);
   if (c->counters_host) (void)hipHostFree(c->counters_host);
   if (c->capture) (void)hipStreamDestroy(c->capture);
+  if (c->icd_cnt) (void)hipFree(c->icd_cnt);
   if (c->mc_tmax) (void)hipFree(c->mc_tmax);
   if (c->mc_q) (void)hipFree(c->mc_q);
   delete c;
@@ -1700,7 +1742,16 @@ int smre_dykstra_project(smre_ctx* c, smre_dtype dt, void* x, int64_t H, int64_t
 int smre_dykstra_incomplete(smre_ctx* c, smre_dtype dt, void* x, int64_t H, int64_t W,
                             int64_t ld, int32_t K, const double* r2, double tol, int32_t mode,
                             int32_t max_inner, int32_t nph, void* stream, smre_report* rep) {
+  return smre_dykstra_incomplete_frames(c, dt, x, H, W, ld, 1, K, r2, tol, mode, max_inner, nph,
+                                        stream, rep);
+}
+
+int smre_dykstra_incomplete_frames(smre_ctx* c, smre_dtype dt, void* x, int64_t H, int64_t W,
+                                   int64_t ld, int64_t frames, int32_t K, const double* r2,
+                                   double tol, int32_t mode, int32_t max_inner, int32_t nph,
+                                   void* stream, smre_report* rep) {
   if (!c || !x || !r2) return SMRE_EINVAL;
+  if (frames < 1 || frames * H > INT32_MAX) return SMRE_EINVAL;
   if (dt != SMRE_F32 && dt != SMRE_F64) return SMRE_EINVAL;
   if (H < 1 || W < 1 || ld < W || H > (1 << 20) || W > (1 << 20)) return SMRE_EINVAL;
   if (K < 0 || K > 5 || max_inner < 1 || nph < 1 || nph > K + 1) return SMRE_EINVAL;
@@ -1714,8 +1765,8 @@ int smre_dykstra_incomplete(smre_ctx* c, smre_dtype dt, void* x, int64_t H, int6
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   if (dt == SMRE_F64)
-    return icd_impl<double>(c, x, H, W, ld, K, r2, tol, mode, max_inner, nph, s, rep);
-  return icd_impl<float>(c, x, H, W, ld, K, r2, tol, mode, max_inner, nph, s, rep);
+    return icd_impl<double>(c, x, H, W, ld, frames, K, r2, tol, mode, max_inner, nph, s, rep);
+  return icd_impl<float>(c, x, H, W, ld, frames, K, r2, tol, mode, max_inner, nph, s, rep);
 }
 
 int smre_batch_workspace_size(smre_dtype dt, int32_t n, const smre_batch_image* im,

@@ -93,3 +93,56 @@ def serve_image(side, child):
 def serve_sides(side):
     """Window sides 1..max(8, side // 64)."""
     return list(range(1, max(8, int(side) // 64) + 1))
+
+
+def blinking_movie(n_frames, H, W, n_e=None, seed=0, mean_count=50.0, psf_sigma=1.5,
+                   exponent=1.5, dtype=np.float32, chunk=256):
+    """Fluorescence fluctuation movie (n_frames, H, W) of blinking emitters.
+
+    Emitters sit at fixed random pixels (n_e = round(H W / 1300) by default).
+    Each one blinks: on- and off-times in frames are drawn from a power law
+    P(tau) ~ tau^-exponent (tau >= 1), its first state at random; an emitter
+    that is on in a frame emits Poisson(mean_count) counts, otherwise none.
+    Frame t is the PSF-blurred fluctuation sum_k (K_kt - <K_k>) G(r - r_k)
+    about each emitter's time-averaged count (Gaussian PSF of psf_sigma px,
+    the same kernel as `emitters`), divided by the movie-wide standard
+    deviation.
+    """
+    rng = rng_for(seed)
+    if n_e is None:
+        n_e = int(round(H * W / 1300.0))
+    rows = rng.integers(0, H, size=n_e)
+    cols = rng.integers(0, W, size=n_e)
+    on = np.zeros((n_e, n_frames), dtype=bool)
+    for k in range(n_e):
+        t, state = 0, bool(rng.integers(0, 2))
+        while t < n_frames:
+            tau = int(np.ceil(rng.random() ** (-1.0 / (exponent - 1.0))))
+            on[k, t:t + tau] = state
+            t += tau
+            state = not state
+    counts = np.where(on, rng.poisson(mean_count, size=on.shape), 0).astype(np.float64)
+    fluct = counts - counts.mean(axis=1, keepdims=True)          # (n_e, n_frames)
+    # PSF stamp: the constant-mode Gaussian filter of a unit impulse
+    rad = int(4.0 * psf_sigma + 0.5)
+    imp = np.zeros((2 * rad + 1, 2 * rad + 1))
+    imp[rad, rad] = 1.0
+    stamp = gaussian_filter(imp, psf_sigma, mode="constant", truncate=4.0)
+    dy, dx = np.meshgrid(np.arange(-rad, rad + 1), np.arange(-rad, rad + 1), indexing="ij")
+    rr = rows[:, None] + dy.ravel()[None, :]
+    cc = cols[:, None] + dx.ravel()[None, :]
+    keep = (rr >= 0) & (rr < H) & (cc >= 0) & (cc < W)
+    kk = np.broadcast_to(np.arange(n_e)[:, None], rr.shape)
+    from scipy.sparse import csr_matrix
+    S = csr_matrix((np.broadcast_to(stamp.ravel(), rr.shape)[keep],
+                    (kk[keep], (rr * W + cc)[keep])), shape=(n_e, H * W))
+    out = np.empty((n_frames, H, W), dtype=dtype)
+    ss = 0.0
+    for f0 in range(0, n_frames, chunk):
+        blk = np.asarray((S.T @ fluct[:, f0:f0 + chunk]).T)     # (frames, H W)
+        ss += float(np.sum(blk * blk))
+        out[f0:f0 + chunk] = blk.reshape(-1, H, W)
+    sd = np.sqrt(ss / (n_frames * H * W))
+    if sd > 0:
+        out /= dtype(sd) if dtype != np.float64 else sd
+    return out
