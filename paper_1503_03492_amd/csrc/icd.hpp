@@ -22,18 +22,26 @@
 
 namespace smre {
 
+// Even bits 0, 2, ..., 10 of a 12-bit Morton index, packed (compaction by
+// masks and shifts).
 __device__ __forceinline__ int morton_x(int m) {
-  int x = 0;
-#pragma unroll
-  for (int b = 0; b < 6; ++b) x |= ((m >> (2 * b)) & 1) << b;
-  return x;
+  unsigned x = (unsigned)m & 0x555u;
+  x = (x | (x >> 1)) & 0x333u;
+  x = (x | (x >> 2)) & 0x0F0Fu;
+  x = (x | (x >> 4)) & 0x00FFu;
+  return (int)x;
 }
 __device__ __forceinline__ int morton_y(int m) { return morton_x(m >> 1); }
 
-// t = sqrt(r2 / n) if n > r2 else 1, in the precision of the image.
-template <typename T> __device__ __forceinline__ T ball_scale(T n, T r2) {
+// t = sqrt(r2 / n) if n > r2 else 1, in the precision of the image.  FP64:
+// the correctly rounded quotient and root.  FP32: sqrt(r2) (computed per
+// level on the host, sr2) times the hardware reciprocal square root of n,
+// clamped to 1 so a window just outside the ball is never scaled up by
+// rounding; one instruction instead of an IEEE divide and square root,
+// within a few ulp.
+template <typename T> __device__ __forceinline__ T ball_scale(T n, T r2, T sr2) {
   if constexpr (sizeof(T) == 8) return n > r2 ? __builtin_sqrt(r2 / n) : T(1);
-  else return n > r2 ? __builtin_sqrtf(r2 / n) : T(1);
+  else return n > r2 ? __builtin_fminf(sr2 * __builtin_amdgcn_rsqf(n), 1.0f) : 1.0f;
 }
 
 template <typename T> __device__ __forceinline__ T wave_max(T v) {
@@ -52,6 +60,7 @@ struct IcdArgs {
   int32_t pad;
   double tol;
   double r2[6];
+  float sr2[6];       // sqrtf((float)r2[k]) for the FP32 scale
   // Work counters (device): kIcdSlots slots of kIcdSlotWords words, one
   // 128-byte line each; a block adds its inner sweeps, square projections
   // and (square, pixel) updates to words 0, 1, 2 of slot (block id mod
@@ -60,7 +69,10 @@ struct IcdArgs {
 };
 constexpr int kIcdSlots = 256, kIcdSlotWords = 16;
 
-template <typename T, int K>
+// MEANABS: stop when the block's sum of |dx| over an inner sweep is at most
+// tol times its pixel count (accumulated per lane in T, summed over the wave
+// in FP64); else when max |dx| < tol.
+template <typename T, int K, bool MEANABS>
 __global__ __launch_bounds__(64) void icd_phase(IcdArgs a) {
   constexpr int B = 1 << K;
   constexpr int NPX = B * B;
@@ -89,12 +101,17 @@ __global__ __launch_bounds__(64) void icd_phase(IcdArgs a) {
   float npf = (float)npix;
   npf = group_sum<64>(npf);
 
-  // active[k][e]: the level-k square holding pixel e lies inside the image.
+  // active[k][e]: the level-k square holding pixel e lies inside the image
+  // (one test per lane when the square holds all of the lane's pixels).
   bool active[K + 1][NPL];
 #pragma unroll
   for (int k = 0; k <= K; ++k)
 #pragma unroll
     for (int e = 0; e < NPL; ++e) {
+      if ((1 << (2 * k)) >= NPL && e > 0) {
+        active[k][e] = active[k][0];
+        continue;
+      }
       const int L = 1 << k;
       const int sy = gy[e] - ((gy[e] - by) & (L - 1));
       const int sx = gx[e] - ((gx[e] - bx) & (L - 1));
@@ -128,12 +145,12 @@ __global__ __launch_bounds__(64) void icd_phase(IcdArgs a) {
 
   int it = 0;
   while (true) {
-    double dsum = 0.0;
-    T dmax = T(0);
+    T dsum = T(0), dmax = T(0);
 #pragma unroll
     for (int k = K; k >= 0; --k) {
       if (k < i) break;
       const T r2 = (T)a.r2[k];
+      const T sr2 = (T)a.sr2[k];
       T y[NPL];
 #pragma unroll
       for (int e = 0; e < NPL; ++e) y[e] = x[e] - q[k][e];
@@ -148,7 +165,7 @@ __global__ __launch_bounds__(64) void icd_phase(IcdArgs a) {
 #pragma unroll
           for (int e = 0; e < NPL; ++e)
             if (e >= e0 && e < e0 + sq) n += y[e] * y[e];
-          const T tt = ball_scale(n, r2);
+          const T tt = ball_scale(n, r2, sr2);
 #pragma unroll
           for (int e = 0; e < NPL; ++e)
             if (e >= e0 && e < e0 + sq) t[e] = tt;
@@ -166,7 +183,7 @@ __global__ __launch_bounds__(64) void icd_phase(IcdArgs a) {
           case 32: n = group_sum<32>(part); break;
           default: n = group_sum<64>(part); break;
         }
-        const T tt = ball_scale(n, r2);
+        const T tt = ball_scale(n, r2, sr2);
 #pragma unroll
         for (int e = 0; e < NPL; ++e) t[e] = tt;
       }
@@ -176,16 +193,16 @@ __global__ __launch_bounds__(64) void icd_phase(IcdArgs a) {
           const T xn = t[e] * y[e];
           q[k][e] = xn - y[e];
           const T d = fabs(x[e] - xn);
-          dsum += (double)d;
-          dmax = fmax(dmax, d);
+          if (MEANABS) dsum += d;
+          else dmax = fmax(dmax, d);
           x[e] = xn;
         }
       }
     }
     ++it;
     bool stop;
-    if (a.mode == 1) {
-      const double s = group_sum<64>(dsum);
+    if (MEANABS) {
+      const double s = group_sum<64>((double)dsum);
       stop = s <= a.tol * (double)npf;
     } else {
       stop = (double)wave_max(dmax) < a.tol;

@@ -517,6 +517,18 @@ int project_impl(smre_ctx* c, smre_dtype dt, void* x, int64_t H, int64_t W, int6
   return SMRE_OK;
 }
 
+template <typename T, bool MEANABS>
+void launch_icd(int K, dim3 grid, const IcdArgs& a, hipStream_t s) {
+  switch (K) {
+    case 0: hipLaunchKernelGGL((icd_phase<T, 0, MEANABS>), grid, dim3(64), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((icd_phase<T, 1, MEANABS>), grid, dim3(64), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((icd_phase<T, 2, MEANABS>), grid, dim3(64), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((icd_phase<T, 3, MEANABS>), grid, dim3(64), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((icd_phase<T, 4, MEANABS>), grid, dim3(64), 0, s, a); break;
+    default: hipLaunchKernelGGL((icd_phase<T, 5, MEANABS>), grid, dim3(64), 0, s, a); break;
+  }
+}
+
 template <bool GEN, typename T>
 int mc_run(smre_ctx* c, const T* fields, int64_t ld, int64_t H, int64_t W, uint64_t seed,
            int64_t f0, int64_t nf, const McSides& sd, double* q_out, double* tmax_out,
@@ -546,7 +558,10 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t fra
   a.mode = mode;
   a.max_inner = max_inner;
   a.tol = tol;
-  for (int k = 0; k <= K; ++k) a.r2[k] = r2[k];
+  for (int k = 0; k <= K; ++k) {
+    a.r2[k] = r2[k];
+    a.sr2[k] = std::sqrt((float)r2[k]);
+  }
   a.counters = c->icd_cnt;
   const int B = 1 << K;
   TimingAcc tacc;
@@ -561,14 +576,10 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t fra
     for (int64_t f0 = 0; f0 < frames; f0 += 65535) {
       const dim3 grid(nbx, nby, (unsigned)std::min<int64_t>(65535, frames - f0));
       a.x = (T*)x + f0 * H * ld;
-      switch (K) {
-        case 0: hipLaunchKernelGGL((icd_phase<T, 0>), grid, dim3(64), 0, s, a); break;
-        case 1: hipLaunchKernelGGL((icd_phase<T, 1>), grid, dim3(64), 0, s, a); break;
-        case 2: hipLaunchKernelGGL((icd_phase<T, 2>), grid, dim3(64), 0, s, a); break;
-        case 3: hipLaunchKernelGGL((icd_phase<T, 3>), grid, dim3(64), 0, s, a); break;
-        case 4: hipLaunchKernelGGL((icd_phase<T, 4>), grid, dim3(64), 0, s, a); break;
-        default: hipLaunchKernelGGL((icd_phase<T, 5>), grid, dim3(64), 0, s, a); break;
-      }
+      if (mode == SMRE_TOL_MEANABS)
+        launch_icd<T, true>(K, grid, a, s);
+      else
+        launch_icd<T, false>(K, grid, a, s);
       HIP_OK(hipGetLastError());
     }
     rc = timing_end(c, tacc, s, slot);
