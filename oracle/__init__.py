@@ -51,6 +51,10 @@ def lib():
                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, dp,
                                  ctypes.POINTER(ctypes.c_int64)]
         L.oracle_icd.restype = ctypes.c_int
+        L.oracle_icd_family.argtypes = [dp, i64, i64, ctypes.c_int32, dp, ctypes.c_double,
+                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ip, ip,
+                                        ip, dp, ctypes.POINTER(ctypes.c_int64)]
+        L.oracle_icd_family.restype = ctypes.c_int
         u64p = ctypes.POINTER(ctypes.c_uint64)
         L.oracle_philox4x64_10.argtypes = [u64p, u64p, u64p]
         L.oracle_philox4x64_10.restype = None
@@ -207,3 +211,31 @@ def order_quantile(q, alpha):
     """ceil(alpha n)-th smallest of the samples q."""
     q = np.ascontiguousarray(q, dtype=np.float64)
     return lib().oracle_order_quantile(_d(q), len(q), float(alpha))
+
+
+def icd_family(x0, K, r2, phases, tol=1e-13, mode=TOL_MAXABS, max_inner=100000):
+    """ICD over a caller-given phase family: phases = [(shift_y, shift_x,
+    min_level), ...].  Returns (z, total_inner_sweeps)."""
+    x0 = np.ascontiguousarray(x0, dtype=np.float64)
+    H, W = x0.shape
+    r2 = np.ascontiguousarray(r2, dtype=np.float64)
+    if len(r2) != K + 1:
+        raise ValueError("need K+1 bounds")
+    sy = np.ascontiguousarray([p[0] for p in phases], dtype=np.int32)
+    sx = np.ascontiguousarray([p[1] for p in phases], dtype=np.int32)
+    lo = np.ascontiguousarray([p[2] for p in phases], dtype=np.int32)
+    z = np.empty_like(x0)
+    tot = ctypes.c_int64(0)
+    rc = lib().oracle_icd_family(_d(x0), H, W, int(K), _d(r2), float(tol), int(mode),
+                                 int(max_inner), len(phases), _i(sy), _i(sx), _i(lo), _d(z),
+                                 ctypes.byref(tot))
+    if rc != 0:
+        raise ValueError("oracle_icd_family rejected its arguments")
+    return z, tot.value
+
+
+def icd_paper_phases(K, num_phases=None):
+    """The paper's family: phase i shifted by 2^i mod 2^K on both axes, levels K..i."""
+    B = 1 << K
+    n = K + 1 if num_phases is None else num_phases
+    return [((1 << i) % B, (1 << i) % B, i) for i in range(n)]

@@ -430,33 +430,46 @@ int oracle_kkt(const double* x0, const double* z, const double* incs, int64_t H,
  * image, with its increments zeroed at the start of the phase.
  * inner_total (optional) receives the sum of inner sweeps over all blocks.
  */
-int oracle_icd(const double* x0, int64_t H, int64_t W, int32_t K, const double* r2, double tol,
-               int32_t mode, int32_t max_inner, int32_t num_phases, double* z,
-               int64_t* inner_total) {
-  if (H < 1 || W < 1 || K < 0 || K > 10 || max_inner < 1 || num_phases < 1 || num_phases > K + 1)
-    return -1;
+/* A family of ICD phases: phase p uses blocks of side 2^K on the lattice
+ * whose origin is shifted by (shift_y[p], shift_x[p]) (0 <= shift < 2^K;
+ * blocks cut by the image edge are clipped) and projects, inside each block,
+ * onto its squares of side 2^k for k = K down to min_level[p] by Dykstra with
+ * increments zeroed at the phase start, until the block converges.  The
+ * paper's family (Sec. 3.2) is phase i = 0..K with both shifts 2^i mod 2^K and
+ * lowest level i; other shifts (e.g. along one axis only) are the variants the
+ * paper leaves open. */
+int oracle_icd_family(const double* x0, int64_t H, int64_t W, int32_t K, const double* r2,
+                      double tol, int32_t mode, int32_t max_inner, int32_t n_phases,
+                      const int32_t* shift_y, const int32_t* shift_x, const int32_t* min_level,
+                      double* z, int64_t* inner_total) {
+  if (H < 1 || W < 1 || K < 0 || K > 10 || max_inner < 1 || n_phases < 1) return -1;
+  int64_t HW = H * W, B = (int64_t)1 << K;
   for (int k = 0; k <= K; ++k)
     if (!(r2[k] > 0.0) || !isfinite(r2[k])) return -1;
-  int64_t HW = H * W, B = (int64_t)1 << K;
+  for (int32_t ph = 0; ph < n_phases; ++ph)
+    if (shift_y[ph] < 0 || shift_y[ph] >= B || shift_x[ph] < 0 || shift_x[ph] >= B ||
+        min_level[ph] < 0 || min_level[ph] > K)
+      return -1;
   double* q = (double*)calloc((size_t)((K + 1) * HW), sizeof(double));
   double* ybuf = (double*)malloc((size_t)(B * B) * sizeof(double));
   if (!q || !ybuf) { free(q); free(ybuf); return -1; }
   if (z != x0) memcpy(z, x0, (size_t)HW * sizeof(double));
   int64_t total = 0;
-  for (int32_t ph = 0; ph < num_phases; ++ph) {
-    int64_t o = ((int64_t)1 << ph) & (B - 1);
-    int64_t start = o > 0 ? o - B : 0;
-    for (int64_t by = start; by < H; by += B)
-      for (int64_t bx = start; bx < W; bx += B) {
+  for (int32_t ph = 0; ph < n_phases; ++ph) {
+    const int lo = min_level[ph];
+    int64_t start_y = shift_y[ph] > 0 ? shift_y[ph] - B : 0;
+    int64_t start_x = shift_x[ph] > 0 ? shift_x[ph] - B : 0;
+    for (int64_t by = start_y; by < H; by += B)
+      for (int64_t bx = start_x; bx < W; bx += B) {
         int64_t ylo = by < 0 ? 0 : by, yhi = by + B < H ? by + B : H;
         int64_t xlo = bx < 0 ? 0 : bx, xhi = bx + B < W ? bx + B : W;
         int64_t npix = (yhi - ylo) * (xhi - xlo);
-        for (int k = ph; k <= K; ++k)
+        for (int k = lo; k <= K; ++k)
           for (int64_t i = ylo; i < yhi; ++i)
             for (int64_t j = xlo; j < xhi; ++j) q[k * HW + i * W + j] = 0.0;
         for (int32_t it = 0; it < max_inner; ++it) {
           double dsum = 0.0, dmax = 0.0;
-          for (int k = K; k >= ph; --k) {
+          for (int k = K; k >= lo; --k) {
             int64_t L = (int64_t)1 << k;
             double* qk = q + k * HW;
             for (int64_t sy = by; sy < by + B; sy += L)
@@ -497,6 +510,21 @@ int oracle_icd(const double* x0, int64_t H, int64_t W, int32_t K, const double* 
   free(q);
   free(ybuf);
   return 0;
+}
+
+/* The paper's ICD (Sec. 3.2): phases i = 0 .. num_phases - 1, both shifts
+ * 2^i mod 2^K, lowest level i. */
+int oracle_icd(const double* x0, int64_t H, int64_t W, int32_t K, const double* r2, double tol,
+               int32_t mode, int32_t max_inner, int32_t num_phases, double* z,
+               int64_t* inner_total) {
+  if (K < 0 || K > 10 || num_phases < 1 || num_phases > K + 1) return -1;
+  int32_t sy[11], sx[11], lo[11];
+  for (int32_t i = 0; i < num_phases; ++i) {
+    sy[i] = sx[i] = (int32_t)(((int64_t)1 << i) & (((int64_t)1 << K) - 1));
+    lo[i] = i;
+  }
+  return oracle_icd_family(x0, H, W, K, r2, tol, mode, max_inner, num_phases, sy, sx, lo, z,
+                           inner_total);
 }
 
 /* ------------------------------------------------------------------------- */

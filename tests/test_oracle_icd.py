@@ -133,3 +133,65 @@ def test_rejects_bad_arguments():
         oracle.icd(np.zeros((8, 8)), 2, [1.0, 1.0, -1.0])
     with pytest.raises(ValueError):
         oracle.icd(np.zeros((8, 8)), 2, [1.0, 1.0, 1.0], num_phases=4)
+
+
+# ---------------------------------------------------------------- phase families
+
+def family_squares(H, W, K, sy, sx, lo, r2):
+    """Squares of one phase of a family: side 2^k (k = lo..K) on the lattice
+    shifted by (sy, sx), inside the image."""
+    B = 1 << K
+    out = []
+    for k in range(lo, K + 1):
+        L = 1 << k
+        y0 = sy - B if sy else 0
+        x0 = sx - B if sx else 0
+        for y in range(y0, H, L):
+            for x in range(x0, W, L):
+                if y >= 0 and x >= 0 and y + L <= H and x + L <= W:
+                    out.append((y, x, L, L, r2[k]))
+    return out
+
+
+def test_paper_family_is_the_icd():
+    K = 3
+    r2 = icd_bounds(K)
+    x0 = gi.emitters(40, 36, n_e=6, seed=3)
+    a, na = oracle.icd(x0, K, r2, tol=1e-12)
+    b, nb = oracle.icd_family(x0, K, r2, oracle.icd_paper_phases(K), tol=1e-12)
+    assert np.array_equal(a, b) and na == nb
+
+
+@pytest.mark.parametrize("H,W,K,phases", [
+    (8, 8, 2, [(1, 0, 0), (0, 1, 0), (2, 2, 1)]),
+    (7, 9, 2, [(0, 0, 0), (1, 0, 1), (0, 3, 1)]),
+    (6, 7, 1, [(1, 0, 0), (0, 1, 1)]),
+])
+def test_family_phases_are_composed_projections(H, W, K, phases):
+    """Off-diagonal families: the composition of brute-force projections onto
+    each phase's set (a mix-up of the two axes fails here)."""
+    r2 = icd_bounds(K)
+    x0 = gi.gaussian(H, W, seed=H * 7 + W, scale=2.5)
+    z, _ = oracle.icd_family(x0, K, r2, phases, tol=1e-14)
+    ref = x0.copy()
+    for sy, sx, lo in phases:
+        ref = project(ref, family_squares(H, W, K, sy, sx, lo, r2))
+    np.testing.assert_allclose(z, ref, atol=1e-10)
+
+
+def test_family_transpose_swaps_shifts():
+    K = 3
+    r2 = icd_bounds(K)
+    x0 = gi.emitters(30, 41, n_e=5, seed=8)
+    ph = [(1, 0, 0), (0, 2, 1), (4, 1, 2)]
+    a, _ = oracle.icd_family(x0, K, r2, ph, tol=1e-13)
+    b, _ = oracle.icd_family(np.ascontiguousarray(x0.T), K, r2, [(x, y, l) for y, x, l in ph],
+                             tol=1e-13)
+    np.testing.assert_allclose(a, b.T, rtol=0, atol=1e-12)
+
+
+def test_family_rejects_bad_phases():
+    with pytest.raises(ValueError):
+        oracle.icd_family(np.zeros((8, 8)), 2, [1.0] * 3, [(4, 0, 0)])
+    with pytest.raises(ValueError):
+        oracle.icd_family(np.zeros((8, 8)), 2, [1.0] * 3, [(0, 0, 3)])
