@@ -168,6 +168,23 @@ int smre_dykstra_incomplete_frames(smre_ctx* ctx, smre_dtype dtype, void* x, int
                                    int32_t max_inner, int32_t num_phases, void* stream,
                                    smre_report* report);
 
+/* The incomplete Dykstra over a caller-given family of phases (the paper's
+ * family is one of them; Sec. 3.2 leaves the choice of subsets open): phase p
+ * uses blocks of side 2^K on the lattice shifted by (shift_y[p], shift_x[p])
+ * (0 <= shift < 2^K; blocks cut by the image edge are clipped) and projects
+ * each block onto its squares of side 2^k, k = K down to min_level[p]
+ * (0 <= min_level <= K), by Dykstra with increments zeroed at the phase start,
+ * until the block meets the stopping rule.  radius2[K+1] bounds a square of
+ * side 2^k.  1 <= n_phases <= 64.  Frames as in
+ * smre_dykstra_incomplete_frames (frames = 1 for one image).  The paper's
+ * family: shift 2^i mod 2^K on both axes and min_level i, i = 0..K. */
+int smre_dykstra_incomplete_family(smre_ctx* ctx, smre_dtype dtype, void* x, int64_t H,
+                                   int64_t W, int64_t ld, int64_t frames, int32_t K,
+                                   const double* radius2, int32_t n_phases,
+                                   const int32_t* shift_y, const int32_t* shift_x,
+                                   const int32_t* min_level, double tol, int32_t tolmode,
+                                   int32_t max_inner, void* stream, smre_report* report);
+
 /* ---- Batches: images of different sizes in one persistent launch per colour ----
  * Each image carries its own sides, bounds, tolerance and sweep cap; the
  * batch shares dtype, increment storage, Kahan flag, check cadence and the

@@ -100,6 +100,9 @@ def _load():
     L.smre_dykstra_incomplete_frames.argtypes = [vp, ctypes.c_int, vp, i64, i64, i64, i64, i32,
                                                  dp, dbl, i32, i32, i32, vp,
                                                  ctypes.POINTER(Report)]
+    L.smre_dykstra_incomplete_family.argtypes = [vp, ctypes.c_int, vp, i64, i64, i64, i64, i32,
+                                                 dp, i32, ip, ip, ip, dbl, i32, i32, vp,
+                                                 ctypes.POINTER(Report)]
     L.smre_max_violation.argtypes = [vp, ctypes.c_int, vp, i64, i64, i64, i32, ip, dp, vp, dp]
     L.smre_batch_workspace_size.argtypes = [ctypes.c_int, i32, ctypes.POINTER(BatchImage),
                                             ctypes.POINTER(BatchParams),
@@ -132,6 +135,7 @@ _lib = _load()
 EXPORTS = ["smre_status_string", "smre_ctx_create", "smre_ctx_destroy", "smre_ctx_set_timing",
            "smre_chi2_bounds", "smre_paper_bounds", "smre_workspace_size",
            "smre_dykstra_project", "smre_dykstra_incomplete", "smre_dykstra_incomplete_frames",
+           "smre_dykstra_incomplete_family",
            "smre_max_violation",
            "smre_batch_workspace_size", "smre_dykstra_project_batch", "smre_serve_create",
            "smre_serve_destroy", "smre_serve_submit", "smre_serve_poll", "smre_serve_stats",
@@ -311,6 +315,34 @@ class Context:
                                                  int(max_inner), int(num_phases), _stream(stream),
                                                  ctypes.byref(rep))
         _check(rc, "smre_dykstra_incomplete_frames")
+        return rep.as_dict()
+
+    def incomplete_family(self, x, K, radius2, phases, tol=1e-3, mode=TOL_MEANABS,
+                          max_inner=10000, stream=None):
+        """ICD over a phase family [(shift_y, shift_x, min_level), ...] on x, a 2-D
+        image or an (n, H, W) stack of frames (CUDA tensor), in place."""
+        import torch
+        if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dim() not in (2, 3):
+            raise TypeError("x must be a 2-D or 3-D CUDA tensor")
+        if x.dim() == 2:
+            n, (H, W, ld) = 1, _image(x)
+        else:
+            if x.stride(2) != 1 or x.stride(0) != x.shape[1] * x.stride(1):
+                raise ValueError("frames must be stacked at stride H * ld")
+            n, H, W, ld = x.shape[0], x.shape[1], x.shape[2], x.stride(1)
+        r, rp = _dvec(radius2)
+        if len(r) != K + 1:
+            raise ValueError("radius2 needs K+1 entries")
+        sy, syp = _ivec([p[0] for p in phases])
+        sx, sxp = _ivec([p[1] for p in phases])
+        lo, lop = _ivec([p[2] for p in phases])
+        rep = Report()
+        rc = _lib.smre_dykstra_incomplete_family(self._h, _dtype_code(x),
+                                                 ctypes.c_void_p(x.data_ptr()), H, W, ld, n,
+                                                 int(K), rp, len(sy), syp, sxp, lop, float(tol),
+                                                 int(mode), int(max_inner), _stream(stream),
+                                                 ctypes.byref(rep))
+        _check(rc, "smre_dykstra_incomplete_family")
         return rep.as_dict()
 
     def project_batch(self, xs, sides, radius2, tol=1e-5, max_sweeps=5000, region=0,

@@ -4,7 +4,9 @@
 // shifted diagonally by 2^i and projects phase by phase: phase i works on
 // blocks of side 2^K on the lattice offset by o_i = 2^i mod 2^K; a block runs
 // Dykstra over its squares of side 2^K, 2^(K-1), ..., 2^i with increments
-// zeroed at the phase start, until the block converges.  Blocks of a phase
+// zeroed at the phase start, until the block converges.  A phase here takes
+// its shift on each axis and its lowest level as arguments, so families
+// other than the paper's (shifts along one axis only, say) run unchanged.  Blocks of a phase
 // are disjoint, so one wave per block runs them all in parallel.
 //
 // A movie of frames (same size, stacked at a fixed stride) runs in the same
@@ -54,7 +56,8 @@ struct IcdArgs {
   int64_t fstride;
   int64_t ld;
   int32_t H, W;
-  int32_t phase;
+  int32_t oy, ox;     // lattice shift of this phase, 0 <= shift < 2^K
+  int32_t lmin;       // lowest level projected in this phase
   int32_t mode;       // 0: max |dx| < tol, 1: sum |dx| <= tol * block pixels
   int32_t max_inner;
   int32_t pad;
@@ -78,10 +81,9 @@ __global__ __launch_bounds__(64) void icd_phase(IcdArgs a) {
   constexpr int NPX = B * B;
   constexpr int NPL = NPX >= 64 ? NPX / 64 : 1;
   const int lane = threadIdx.x;
-  const int i = a.phase;
-  const int o = (1 << i) & (B - 1);
-  const int by = (o > 0 ? o - B : 0) + (int)blockIdx.y * B;
-  const int bx = (o > 0 ? o - B : 0) + (int)blockIdx.x * B;
+  const int i = a.lmin;
+  const int by = (a.oy > 0 ? a.oy - B : 0) + (int)blockIdx.y * B;
+  const int bx = (a.ox > 0 ? a.ox - B : 0) + (int)blockIdx.x * B;
   T* xg = (T*)a.x + (int64_t)blockIdx.z * a.fstride;
 
   T x[NPL];

@@ -535,10 +535,11 @@ int mc_run(smre_ctx* c, const T* fields, int64_t ld, int64_t H, int64_t W, uint6
            hipStream_t s, TimingAcc& acc);
 int mc_sides(int32_t n, const int32_t* sides, int64_t H, int64_t W, McSides* sd);
 
+// Phase p: lattice shift (sy[p], sx[p]), levels K down to lo[p].
 template <typename T>
 int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t frames, int K,
-             const double* r2, double tol, int mode, int max_inner, int nph, hipStream_t s,
-             smre_report* rep) {
+             const double* r2, double tol, int mode, int max_inner, int nph, const int32_t* sy,
+             const int32_t* sx, const int32_t* lo, hipStream_t s, smre_report* rep) {
   HIP_OK(hipEventRecord(c->t0, s));
   hipLaunchKernelGGL(ctrl_reset_kernel, dim3(1), dim3(1), 0, s, c->ctrl);
   bool bad = false;
@@ -566,10 +567,11 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t fra
   const int B = 1 << K;
   TimingAcc tacc;
   for (int ph = 0; ph < nph; ++ph) {
-    a.phase = ph;
-    const int o = (1 << ph) & (B - 1);
-    const int start = o > 0 ? o - B : 0;
-    const int nby = (int)((H - start + B - 1) / B), nbx = (int)((W - start + B - 1) / B);
+    a.oy = sy[ph];
+    a.ox = sx[ph];
+    a.lmin = lo[ph];
+    const int start_y = sy[ph] > 0 ? sy[ph] - B : 0, start_x = sx[ph] > 0 ? sx[ph] - B : 0;
+    const int nby = (int)((H - start_y + B - 1) / B), nbx = (int)((W - start_x + B - 1) / B);
     int slot;
     rc = timing_begin(c, tacc, s, &slot);
     if (rc) return rc;
@@ -1761,11 +1763,31 @@ int smre_dykstra_incomplete_frames(smre_ctx* c, smre_dtype dt, void* x, int64_t 
                                    int64_t ld, int64_t frames, int32_t K, const double* r2,
                                    double tol, int32_t mode, int32_t max_inner, int32_t nph,
                                    void* stream, smre_report* rep) {
-  if (!c || !x || !r2) return SMRE_EINVAL;
+  if (K < 0 || K > 5 || nph < 1 || nph > K + 1) return SMRE_EINVAL;
+  int32_t sy[6], sx[6], lo[6];
+  for (int i = 0; i < nph; ++i) {
+    sy[i] = sx[i] = (1 << i) & ((1 << K) - 1);
+    lo[i] = i;
+  }
+  return smre_dykstra_incomplete_family(c, dt, x, H, W, ld, frames, K, r2, nph, sy, sx, lo, tol,
+                                        mode, max_inner, stream, rep);
+}
+
+int smre_dykstra_incomplete_family(smre_ctx* c, smre_dtype dt, void* x, int64_t H, int64_t W,
+                                   int64_t ld, int64_t frames, int32_t K, const double* r2,
+                                   int32_t n_phases, const int32_t* shift_y,
+                                   const int32_t* shift_x, const int32_t* min_level, double tol,
+                                   int32_t mode, int32_t max_inner, void* stream,
+                                   smre_report* rep) {
+  if (!c || !x || !r2 || !shift_y || !shift_x || !min_level) return SMRE_EINVAL;
   if (frames < 1 || frames * H > INT32_MAX) return SMRE_EINVAL;
   if (dt != SMRE_F32 && dt != SMRE_F64) return SMRE_EINVAL;
   if (H < 1 || W < 1 || ld < W || H > (1 << 20) || W > (1 << 20)) return SMRE_EINVAL;
-  if (K < 0 || K > 5 || max_inner < 1 || nph < 1 || nph > K + 1) return SMRE_EINVAL;
+  if (K < 0 || K > 5 || max_inner < 1 || n_phases < 1 || n_phases > 64) return SMRE_EINVAL;
+  for (int p = 0; p < n_phases; ++p)
+    if (shift_y[p] < 0 || shift_y[p] >= (1 << K) || shift_x[p] < 0 || shift_x[p] >= (1 << K) ||
+        min_level[p] < 0 || min_level[p] > K)
+      return SMRE_EINVAL;
   if (mode != SMRE_TOL_MAXABS && mode != SMRE_TOL_MEANABS) return SMRE_EINVAL;
   if (!std::isfinite(tol)) return SMRE_EINVAL;
   for (int k = 0; k <= K; ++k) {
@@ -1776,8 +1798,10 @@ int smre_dykstra_incomplete_frames(smre_ctx* c, smre_dtype dt, void* x, int64_t 
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   if (dt == SMRE_F64)
-    return icd_impl<double>(c, x, H, W, ld, frames, K, r2, tol, mode, max_inner, nph, s, rep);
-  return icd_impl<float>(c, x, H, W, ld, frames, K, r2, tol, mode, max_inner, nph, s, rep);
+    return icd_impl<double>(c, x, H, W, ld, frames, K, r2, tol, mode, max_inner, n_phases,
+                            shift_y, shift_x, min_level, s, rep);
+  return icd_impl<float>(c, x, H, W, ld, frames, K, r2, tol, mode, max_inner, n_phases, shift_y,
+                         shift_x, min_level, s, rep);
 }
 
 int smre_batch_workspace_size(smre_dtype dt, int32_t n, const smre_batch_image* im,

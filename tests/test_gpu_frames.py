@@ -137,3 +137,45 @@ def test_frames_reject_bad_arguments(ctx, smre):
     x[1, 3, 3] = float("nan")
     with pytest.raises(smre.SmreError):
         ctx.incomplete_frames(x, 2, bounds(2))
+
+
+# ---------------------------------------------------------------- phase families
+
+@pytest.mark.parametrize("H,W,K,phases", [
+    (70, 45, 3, [(1, 0, 0), (0, 1, 0), (2, 0, 1), (0, 2, 1), (4, 4, 2)]),
+    (37, 53, 2, [(0, 0, 0), (1, 0, 1), (0, 3, 1), (2, 1, 0)]),
+    (64, 64, 4, [(1, 1, 0), (2, 0, 1), (0, 2, 1), (8, 8, 3), (0, 0, 4)]),
+    (33, 96, 5, [(16, 0, 2), (0, 16, 3), (5, 7, 0)]),
+])
+def test_family_fp64_matches_oracle(ctx, H, W, K, phases):
+    print(f"family fp64 {H}x{W} K={K} {phases}", flush=True)
+    x0 = gi.emitters(H, W, n_e=max(3, H * W // 400), seed=K + H)
+    r2 = bounds(K)
+    ref, n_ref = oracle.icd_family(x0, K, r2, phases, tol=1e-13, max_inner=100000)
+    x = torch.from_numpy(x0.copy()).cuda()
+    rep = ctx.incomplete_family(x, K, r2, phases, tol=1e-13, mode=0, max_inner=100000)
+    assert relerr(x.cpu().numpy(), ref) <= 1e-10
+    assert rep["inner_sweeps"] == n_ref
+
+
+def test_family_paper_phases_equal_incomplete(ctx):
+    # the paper's family through the family entry point = the ICD call, bitwise
+    n, H, W, K = 3, 64, 80, 4
+    movie = gi.blinking_movie(n, H, W, n_e=10, seed=2)
+    r2 = bounds(K)
+    a = torch.from_numpy(movie).cuda()
+    b = a.clone()
+    ra = ctx.incomplete_frames(a, K, r2, tol=1e-3, mode=1)
+    rb = ctx.incomplete_family(b, K, r2, oracle.icd_paper_phases(K), tol=1e-3, mode=1)
+    assert torch.equal(a, b)
+    assert ra["inner_sweeps"] == rb["inner_sweeps"]
+
+
+def test_family_rejects_bad_phases(ctx, smre):
+    x = torch.zeros((16, 16), dtype=torch.float64, device="cuda")
+    with pytest.raises(smre.SmreError):
+        ctx.incomplete_family(x, 2, bounds(2), [(4, 0, 0)])
+    with pytest.raises(smre.SmreError):
+        ctx.incomplete_family(x, 2, bounds(2), [(0, 0, 3)])
+    with pytest.raises(smre.SmreError):
+        ctx.incomplete_family(x, 2, bounds(2), [])
