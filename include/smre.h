@@ -322,6 +322,56 @@ int smre_mc_quantile(smre_ctx* ctx, int64_t H, int64_t W, int32_t n_sides, const
                      uint64_t seed, int64_t n_fields, double alpha, double* q_alpha, void* stream,
                      smre_report* report);
 
+/* ---- ADMM outer loop (Sec. 2.2, Algorithm 1, split form) ----
+ * Minimises G(eps) + lam/2 ||z||^2 subject to I = A x + eps and z = x, where
+ * A is a Gaussian PSF of width sigma px (zero outside the image; taps
+ * k = -R..R with R = floor(4 sigma + 1/2) <= 32, weights exp(-k^2 / (2 sigma^2))
+ * normalised to sum 1; sigma = 0 is the identity) and G the multi-resolution
+ * constraint.  Starting from x = eps = z = Y1 = Y2 = 0, each iteration:
+ *   x   <- x - (-A (rho1 (I - A x - eps) + Y1) + rho2 (x - z) + Y2) / (2 gamma)
+ *   eps  = P_G(I - A x + Y1 / rho1)      (ICD or full Dykstra, below)
+ *   z    = (rho2 x + Y2) / (lam + rho2)
+ *   Y1  += alpha1 (I - A x - eps),  Y2 += alpha2 (x - z)
+ * and it stops once ||x_new - x||_2 <= delta and ||I - A x - eps||_2 <= delta
+ * (FP64 sums), or after max_iter iterations.  The defaults of the paper's
+ * parameter file: rho1 6.192, rho2 1.8, alpha1 1.2, alpha2 0.12, lam 1. */
+typedef enum { SMRE_ADMM_ICD = 0, SMRE_ADMM_FULL = 1 } smre_admm_method;
+
+typedef struct {
+  double sigma, lam, rho1, rho2, alpha1, alpha2;
+  double gamma;          /* x-step stabilisation; <= 0: (rho1 + rho2) / 2 */
+  double delta;          /* stopping threshold; < 0: run exactly max_iter */
+  int32_t max_iter;      /* >= 1 */
+  int32_t method;        /* smre_admm_method */
+  /* ICD projection: K, radius2_icd[K+1], the inner rule (tolmode, tol, cap) */
+  int32_t K;
+  int32_t icd_tolmode;
+  double icd_tol;
+  int32_t icd_max_inner;
+  int32_t reserved;
+  const double* radius2_icd;
+  /* full projection: sides, radius2, tol, max_sweeps, ... (smre_params) */
+  const smre_params* full;
+} smre_admm_params;
+
+typedef struct {
+  int32_t iterations;    /* iterations run */
+  int32_t converged;     /* 1 if the delta rule stopped it */
+  double last_dx;        /* ||x_new - x||_2 of the last iteration */
+  double last_residual;  /* ||I - A x - eps||_2 of the last iteration */
+  double elapsed_ms;     /* wall time of the call */
+  double projection_ms;  /* of which in the projections (host clock) */
+  int64_t projection_sweeps;  /* inner sweeps (ICD) or sweeps (full), summed */
+} smre_admm_report;
+
+/* I: device image (dtype, row stride ld), read only; x: device output (same
+ * layout), the estimate.  eps_out (device, same layout, may be NULL): the
+ * final eps.  H, W <= 65535.  Errors as for the projections; SMRE_ENOMEM if
+ * the working set (10 images) cannot be allocated. */
+int smre_admm(smre_ctx* ctx, smre_dtype dtype, const void* I, void* x, int64_t H, int64_t W,
+              int64_t ld, const smre_admm_params* p, void* eps_out, void* stream,
+              smre_admm_report* report);
+
 #ifdef __cplusplus
 }
 #endif

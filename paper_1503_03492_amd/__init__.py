@@ -75,6 +75,31 @@ class ServeCounters(ctypes.Structure):
                                               "active", "queued", "sweeps", "bytes_in_use")]
 
 
+class AdmmParams(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_double), ("lam", ctypes.c_double), ("rho1", ctypes.c_double),
+                ("rho2", ctypes.c_double), ("alpha1", ctypes.c_double),
+                ("alpha2", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("delta", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("method", ctypes.c_int32), ("K", ctypes.c_int32),
+                ("icd_tolmode", ctypes.c_int32), ("icd_tol", ctypes.c_double),
+                ("icd_max_inner", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("radius2_icd", ctypes.POINTER(ctypes.c_double)),
+                ("full", ctypes.POINTER(Params))]
+
+
+class AdmmReport(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("last_dx", ctypes.c_double), ("last_residual", ctypes.c_double),
+                ("elapsed_ms", ctypes.c_double), ("projection_ms", ctypes.c_double),
+                ("projection_sweeps", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+ADMM_ICD, ADMM_FULL = 0, 1
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
@@ -119,6 +144,8 @@ def _load():
                                   ctypes.c_size_t, ctypes.POINTER(Report),
                                   ctypes.POINTER(ctypes.c_double)]
     L.smre_serve_stats.argtypes = [vp, ctypes.POINTER(ServeCounters)]
+    L.smre_admm.argtypes = [vp, ctypes.c_int, vp, vp, i64, i64, i64, ctypes.POINTER(AdmmParams),
+                            vp, vp, ctypes.POINTER(AdmmReport)]
     u64 = ctypes.c_uint64
     L.smre_mc_fields.argtypes = [vp, i64, i64, u64, i64, i64, vp, i64, vp]
     L.smre_mc_statistic.argtypes = [vp, i64, i64, i32, ip, u64, i64, i64, dp, dp, vp,
@@ -139,7 +166,8 @@ EXPORTS = ["smre_status_string", "smre_ctx_create", "smre_ctx_destroy", "smre_ct
            "smre_max_violation",
            "smre_batch_workspace_size", "smre_dykstra_project_batch", "smre_serve_create",
            "smre_serve_destroy", "smre_serve_submit", "smre_serve_poll", "smre_serve_stats",
-           "smre_mc_fields", "smre_mc_statistic", "smre_mc_statistic_fields", "smre_mc_quantile"]
+           "smre_mc_fields", "smre_mc_statistic", "smre_mc_statistic_fields", "smre_mc_quantile",
+           "smre_admm"]
 
 
 def lib():
@@ -389,6 +417,43 @@ class Context:
                                        W, ld, len(s), sp, rp, _stream(stream), ctypes.byref(out)),
                "smre_max_violation")
         return out.value
+
+    # ---- ADMM outer loop ----
+    def admm(self, I, sigma, method=ADMM_ICD, K=4, radius2_icd=None, icd_tol=1e-3,
+             icd_mode=TOL_MEANABS, icd_max_inner=10000, sides=None, radius2=None, full_tol=1e-5,
+             full_max_sweeps=5000, lam=1.0, rho1=6.192, rho2=1.8, alpha1=1.2, alpha2=0.12,
+             gamma=0.0, delta=1e-3, max_iter=100, want_eps=False, stream=None):
+        """ADMM estimate x (new tensor like I) for the data I (2-D CUDA tensor);
+        returns (x, report) or (x, eps, report)."""
+        import torch
+        H, W, ld = _image(I)
+        x = torch.empty_strided(I.size(), I.stride(), dtype=I.dtype, device=I.device)
+        eps = (torch.empty_strided(I.size(), I.stride(), dtype=I.dtype, device=I.device)
+               if want_eps else None)
+        keep = []
+        p = AdmmParams(float(sigma), float(lam), float(rho1), float(rho2), float(alpha1),
+                       float(alpha2), float(gamma), float(delta), int(max_iter), int(method),
+                       int(K), int(icd_mode), float(icd_tol), int(icd_max_inner), 0, None, None)
+        if method == ADMM_ICD:
+            r, rp = _dvec(radius2_icd)
+            keep.append(r)
+            p.radius2_icd = rp
+        else:
+            s_, sp = _ivec(sides)
+            r, rp = _dvec(radius2)
+            keep += [s_, r]
+            fp = Params(len(s_), sp, rp, float(full_tol), int(full_max_sweeps), 1, 0, INC_SAME,
+                        1, 0, 1e-5)
+            keep.append(fp)
+            p.full = ctypes.pointer(fp)
+        rep = AdmmReport()
+        _check(_lib.smre_admm(self._h, _dtype_code(I), ctypes.c_void_p(I.data_ptr()),
+                              ctypes.c_void_p(x.data_ptr()), H, W, ld, ctypes.byref(p),
+                              ctypes.c_void_p(eps.data_ptr()) if eps is not None else None,
+                              _stream(stream), ctypes.byref(rep)), "smre_admm")
+        if want_eps:
+            return x, eps, rep.as_dict()
+        return x, rep.as_dict()
 
     # ---- Monte-Carlo weights (the paper's q_alpha) ----
     def mc_fields(self, out, seed, field0=0, stream=None):

@@ -25,6 +25,7 @@
 #include "checks.hpp"
 #include "kernels.hpp"
 #include "mc.hpp"
+#include "admm.hpp"
 #include "serve_core.hpp"
 #include "smre.h"
 
@@ -65,6 +66,9 @@ struct smre_ctx {
   unsigned long long* icd_cnt = nullptr;  // ICD work counters (kIcdSlots lines)
   unsigned long long* mc_tmax = nullptr;  // Monte-Carlo per-(field, side) maxima
   double* mc_q = nullptr;                 // Monte-Carlo statistic per field
+  void* admm_ws = nullptr;                // ADMM working images
+  size_t admm_bytes = 0;
+  double* admm_slots = nullptr;           // ADMM norm partials (2 x kAdmmSlots lines)
 };
 
 namespace {
@@ -539,14 +543,20 @@ int mc_sides(int32_t n, const int32_t* sides, int64_t H, int64_t W, McSides* sd)
 template <typename T>
 int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t frames, int K,
              const double* r2, double tol, int mode, int max_inner, int nph, const int32_t* sy,
-             const int32_t* sx, const int32_t* lo, hipStream_t s, smre_report* rep) {
+             const int32_t* sx, const int32_t* lo, hipStream_t s, smre_report* rep,
+             bool checks = true) {
+  // checks: the non-finite test of the input and the feasibility report (an
+  // inner call of the ADMM loop, whose inputs are its own, skips both)
   HIP_OK(hipEventRecord(c->t0, s));
-  hipLaunchKernelGGL(ctrl_reset_kernel, dim3(1), dim3(1), 0, s, c->ctrl);
-  bool bad = false;
-  // frames are stacked H * ld elements apart: one tall image of frames * H rows
-  int rc = check_nonfinite<T>(c, x, frames * H, W, ld, s, &bad);
-  if (rc) return rc;
-  if (bad) return SMRE_ENONFINITE;
+  int rc = SMRE_OK;
+  if (checks) {
+    hipLaunchKernelGGL(ctrl_reset_kernel, dim3(1), dim3(1), 0, s, c->ctrl);
+    bool bad = false;
+    // frames are stacked H * ld elements apart: one tall image of frames * H rows
+    rc = check_nonfinite<T>(c, x, frames * H, W, ld, s, &bad);
+    if (rc) return rc;
+    if (bad) return SMRE_ENONFINITE;
+  }
   constexpr int64_t kCntWords = (int64_t)kIcdSlots * kIcdSlotWords;
   if (!c->icd_cnt) HIP_OK(hipMalloc(&c->icd_cnt, sizeof(unsigned long long) * kCntWords));
   hipLaunchKernelGGL((fill_kernel<unsigned long long>), dim3(grid_for(kCntWords)), dim3(256), 0,
@@ -600,25 +610,28 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t fra
   // position, every frame), i.e. how far ICD is from feasibility for the
   // exact method: the largest window sum of each (frame, side) from the
   // all-sides tile kernel, then the worst ratio to its bound.
-  std::vector<int32_t> fam;
-  std::vector<double> fam_r2;
-  for (int k = 0; k <= K; ++k)
-    if ((1 << k) <= H && (1 << k) <= W) {
-      fam.push_back(1 << k);
-      fam_r2.push_back(r2[k]);
-    }
-  McSides sd;
-  rc = mc_sides((int32_t)fam.size(), fam.data(), H, W, &sd);
-  if (rc) return rc;
-  std::vector<double> qf((size_t)frames), tmax((size_t)frames * fam.size());
-  TimingAcc vacc;
-  rc = mc_run<false, T>(c, (const T*)x, ld, H, W, 0, 0, frames, sd, qf.data(), tmax.data(), s,
-                        vacc);
-  if (rc) return rc;
-  double viol = -INFINITY;
-  for (int64_t f = 0; f < frames; ++f)
-    for (size_t k = 0; k < fam.size(); ++k)
-      viol = std::max(viol, tmax[(size_t)f * fam.size() + k] / fam_r2[k] - 1.0);
+  double viol = NAN;
+  if (checks) {
+    std::vector<int32_t> fam;
+    std::vector<double> fam_r2;
+    for (int k = 0; k <= K; ++k)
+      if ((1 << k) <= H && (1 << k) <= W) {
+        fam.push_back(1 << k);
+        fam_r2.push_back(r2[k]);
+      }
+    McSides sd;
+    rc = mc_sides((int32_t)fam.size(), fam.data(), H, W, &sd);
+    if (rc) return rc;
+    std::vector<double> qf((size_t)frames), tmax((size_t)frames * fam.size());
+    TimingAcc vacc;
+    rc = mc_run<false, T>(c, (const T*)x, ld, H, W, 0, 0, frames, sd, qf.data(), tmax.data(), s,
+                          vacc);
+    if (rc) return rc;
+    viol = -INFINITY;
+    for (int64_t f = 0; f < frames; ++f)
+      for (size_t k = 0; k < fam.size(); ++k)
+        viol = std::max(viol, tmax[(size_t)f * fam.size() + k] / fam_r2[k] - 1.0);
+  }
   HIP_OK(hipEventRecord(c->t1, s));
   HIP_OK(hipEventSynchronize(c->t1));
   float ms = 0.f;
@@ -1623,6 +1636,157 @@ int mc_statistic_gen(smre_ctx* c, int64_t H, int64_t W, const McSides& sd, uint6
   return SMRE_OK;
 }
 
+// ---------------------------------------------------------------- ADMM
+int psf_weights(double sigma, PsfWeights* pw) {
+  std::memset(pw, 0, sizeof(*pw));
+  if (!(sigma >= 0) || !std::isfinite(sigma)) return SMRE_EINVAL;
+  if (sigma == 0) {
+    pw->R = 0;
+    pw->w[0] = 1.0;
+    return SMRE_OK;
+  }
+  const int R = (int)(4.0 * sigma + 0.5);
+  if (R > kAdmmMaxRadius) return SMRE_EINVAL;
+  double sum = 0.0;
+  for (int k = -R; k <= R; ++k) sum += std::exp(-0.5 * (double)k * k / (sigma * sigma));
+  for (int k = 0; k <= R; ++k) pw->w[k] = std::exp(-0.5 * (double)k * k / (sigma * sigma)) / sum;
+  pw->R = R;
+  return SMRE_OK;
+}
+
+template <typename T>
+int blur(const T* in, T* tmp, T* out, int H, int W, const PsfWeights& pw, hipStream_t s) {
+  hipLaunchKernelGGL((blur_rows<T>), dim3((W + 255) / 256, H), dim3(256), 0, s, in, tmp, H, W,
+                     (int64_t)W, pw);
+  hipLaunchKernelGGL((blur_cols<T>), dim3((W + 63) / 64, (H + 63) / 64), dim3(256), 0, s, tmp,
+                     out, H, W, (int64_t)W, pw);
+  HIP_OK(hipGetLastError());
+  return SMRE_OK;
+}
+
+template <typename T>
+int admm_impl(smre_ctx* c, smre_dtype dt, const T* I_user, T* x_user, int64_t H, int64_t W,
+              int64_t ld, const smre_admm_params* p, T* eps_user, hipStream_t s,
+              smre_admm_report* rep) {
+  const double t_start = smre_serve::now_s();
+  PsfWeights pw;
+  int rc = psf_weights(p->sigma, &pw);
+  if (rc) return rc;
+  const int64_t n = H * W;
+  const size_t img = align_up((size_t)n * sizeof(T), 256);
+  const size_t need = 10 * img;
+  if (c->admm_bytes < need) {
+    if (c->admm_ws) HIP_OK(hipFree(c->admm_ws));
+    c->admm_ws = nullptr;
+    c->admm_bytes = 0;
+    if (hipMalloc(&c->admm_ws, need) != hipSuccess) return SMRE_ENOMEM;
+    c->admm_bytes = need;
+  }
+  if (!c->admm_slots)
+    HIP_OK(hipMalloc(&c->admm_slots, sizeof(double) * 2 * kAdmmSlots * kAdmmSlotWords));
+  unsigned char* base = (unsigned char*)c->admm_ws;
+  T* I = (T*)(base + 0 * img);
+  T* x = (T*)(base + 1 * img);
+  T* z = (T*)(base + 2 * img);
+  T* eps = (T*)(base + 3 * img);
+  T* Y1 = (T*)(base + 4 * img);
+  T* Y2 = (T*)(base + 5 * img);
+  T* Ax = (T*)(base + 6 * img);
+  T* t = (T*)(base + 7 * img);
+  T* At = (T*)(base + 8 * img);
+  T* tmp = (T*)(base + 9 * img);
+  HIP_OK(hipMemcpy2DAsync(I, W * sizeof(T), I_user, ld * sizeof(T), W * sizeof(T), H,
+                          hipMemcpyDeviceToDevice, s));
+  // x = z = eps = Y1 = Y2 = 0, hence A x = 0
+  hipLaunchKernelGGL((fill_kernel<T>), dim3(grid_for(6 * (int64_t)(img / sizeof(T)))), dim3(256),
+                     0, s, x, (int64_t)(6 * (img / sizeof(T))), T(0));
+  bool bad = false;
+  rc = check_nonfinite<T>(c, I, H, W, W, s, &bad);
+  if (rc) return rc;
+  if (bad) return SMRE_ENONFINITE;
+  AdmmCoef cf;
+  cf.rho1 = p->rho1;
+  cf.rho2 = p->rho2;
+  cf.lam = p->lam;
+  cf.alpha1 = p->alpha1;
+  cf.alpha2 = p->alpha2;
+  cf.inv2g = 1.0 / (2.0 * (p->gamma > 0 ? p->gamma : 0.5 * (p->rho1 + p->rho2)));
+  double* slots_dx = c->admm_slots;
+  double* slots_res = c->admm_slots + kAdmmSlots * kAdmmSlotWords;
+  const int64_t nslot = 2 * kAdmmSlots * kAdmmSlotWords;
+  std::vector<double> host((size_t)nslot);
+  int32_t sy[6], sx[6], lo[6];
+  for (int i = 0; i <= p->K && i < 6; ++i) {
+    sy[i] = sx[i] = (1 << i) & ((1 << p->K) - 1);
+    lo[i] = i;
+  }
+  const dim3 eg(grid_for(n)), eb(256);
+  double proj_s = 0.0, dx = 0.0, res = 0.0;
+  int64_t psweeps = 0;
+  int it = 0;
+  bool conv = false;
+  for (it = 1; it <= p->max_iter; ++it) {
+    hipLaunchKernelGGL((fill_kernel<double>), dim3(grid_for(nslot)), dim3(256), 0, s,
+                       c->admm_slots, nslot, 0.0);
+    hipLaunchKernelGGL((admm_coupling<T>), eg, eb, 0, s, n, I, Ax, eps, Y1, t, cf);
+    rc = blur<T>(t, tmp, At, (int)H, (int)W, pw, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL((admm_x_step<T>), eg, eb, 0, s, n, x, At, z, Y2, cf, slots_dx);
+    rc = blur<T>(x, tmp, Ax, (int)H, (int)W, pw, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL((admm_eps_input<T>), eg, eb, 0, s, n, I, Ax, Y1, eps, cf);
+    HIP_OK(hipGetLastError());
+    const double tp = smre_serve::now_s();
+    smre_report pr;
+    std::memset(&pr, 0, sizeof(pr));
+    if (p->method == SMRE_ADMM_ICD) {
+      rc = icd_impl<T>(c, eps, H, W, W, 1, p->K, p->radius2_icd, p->icd_tol, p->icd_tolmode,
+                       p->icd_max_inner, p->K + 1, sy, sx, lo, s, &pr, false);
+      if (rc) return rc;
+      psweeps += pr.inner_sweeps;
+    } else {
+      rc = smre_dykstra_project(c, dt, eps, H, W, W, p->full, nullptr, 0, s, &pr);
+      if (rc != SMRE_OK && rc != SMRE_NOT_CONVERGED) return rc;
+      psweeps += pr.sweeps;
+    }
+    proj_s += smre_serve::now_s() - tp;
+    hipLaunchKernelGGL((admm_finish<T>), eg, eb, 0, s, n, I, x, Ax, eps, z, Y1, Y2, cf,
+                       slots_res);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(host.data(), c->admm_slots, sizeof(double) * nslot,
+                          hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    double sdx = 0.0, sres = 0.0;
+    for (int k = 0; k < kAdmmSlots; ++k) {
+      sdx += host[(size_t)k * kAdmmSlotWords];
+      sres += host[(size_t)(kAdmmSlots + k) * kAdmmSlotWords];
+    }
+    dx = std::sqrt(sdx);
+    res = std::sqrt(sres);
+    if (dx <= p->delta && res <= p->delta) {
+      conv = true;
+      break;
+    }
+  }
+  if (it > p->max_iter) it = p->max_iter;
+  HIP_OK(hipMemcpy2DAsync(x_user, ld * sizeof(T), x, W * sizeof(T), W * sizeof(T), H,
+                          hipMemcpyDeviceToDevice, s));
+  if (eps_user)
+    HIP_OK(hipMemcpy2DAsync(eps_user, ld * sizeof(T), eps, W * sizeof(T), W * sizeof(T), H,
+                            hipMemcpyDeviceToDevice, s));
+  HIP_OK(hipStreamSynchronize(s));
+  if (rep) {
+    rep->iterations = it;
+    rep->converged = conv ? 1 : 0;
+    rep->last_dx = dx;
+    rep->last_residual = res;
+    rep->elapsed_ms = (smre_serve::now_s() - t_start) * 1e3;
+    rep->projection_ms = proj_s * 1e3;
+    rep->projection_sweeps = psweeps;
+  }
+  return SMRE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1677,6 +1841,8 @@ void smre_ctx_destroy(smre_ctx* c) {
   if (c->counters_host) (void)hipHostFree(c->counters_host);
   if (c->capture) (void)hipStreamDestroy(c->capture);
   if (c->icd_cnt) (void)hipFree(c->icd_cnt);
+  if (c->admm_ws) (void)hipFree(c->admm_ws);
+  if (c->admm_slots) (void)hipFree(c->admm_slots);
   if (c->mc_tmax) (void)hipFree(c->mc_tmax);
   if (c->mc_q) (void)hipFree(c->mc_q);
   delete c;
@@ -1941,6 +2107,37 @@ int smre_mc_quantile(smre_ctx* c, int64_t H, int64_t W, int32_t n_sides, const i
   std::nth_element(q.begin(), q.begin() + (k - 1), q.end());
   *q_alpha = q[(size_t)(k - 1)];
   return SMRE_OK;
+}
+
+int smre_admm(smre_ctx* c, smre_dtype dt, const void* I, void* x, int64_t H, int64_t W,
+              int64_t ld, const smre_admm_params* p, void* eps_out, void* stream,
+              smre_admm_report* rep) {
+  if (!c || !I || !x || !p) return SMRE_EINVAL;
+  if (dt != SMRE_F32 && dt != SMRE_F64) return SMRE_EINVAL;
+  if (H < 1 || W < 1 || ld < W || H > 65535 || W > 65535) return SMRE_EINVAL;
+  if (!(p->lam > 0) || !(p->rho1 > 0) || !(p->rho2 > 0) || !(p->alpha1 > 0) ||
+      !(p->alpha2 > 0) || !std::isfinite(p->gamma) || !std::isfinite(p->delta) ||
+      p->max_iter < 1)
+    return SMRE_EINVAL;
+  if (p->method == SMRE_ADMM_ICD) {
+    if (p->K < 0 || p->K > 5 || !p->radius2_icd || p->icd_max_inner < 1) return SMRE_EINVAL;
+    if (p->icd_tolmode != SMRE_TOL_MAXABS && p->icd_tolmode != SMRE_TOL_MEANABS)
+      return SMRE_EINVAL;
+    for (int k = 0; k <= p->K; ++k)
+      if (!(p->radius2_icd[k] > 0) || !std::isfinite(p->radius2_icd[k])) return SMRE_EINVAL;
+  } else if (p->method == SMRE_ADMM_FULL) {
+    if (!p->full) return SMRE_EINVAL;
+  } else {
+    return SMRE_EINVAL;
+  }
+  int rc = set_device(c);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (dt == SMRE_F64)
+    return admm_impl<double>(c, dt, (const double*)I, (double*)x, H, W, ld, p, (double*)eps_out,
+                             s, rep);
+  return admm_impl<float>(c, dt, (const float*)I, (float*)x, H, W, ld, p, (float*)eps_out, s,
+                          rep);
 }
 
 struct smre_server {
