@@ -445,6 +445,64 @@ def icd_offdiagonal_phases(K):
     return out
 
 
+def bench_admm(args):
+    """The paper's timing experiment: 100 ADMM iterations on a 512^2 deblurring
+    problem (synthetic piecewise-smooth scene standing in for the test image,
+    Gaussian PSF of 4 px, noise of one gray level), the projection by ICD
+    (K = 4, squares of side 1..16, the paper's tolerance 1e-3 mean-abs), FP32,
+    the paper's ADMM parameters; a few iterations with the exact projection
+    (sides 1..15, tol 1e-3) for the per-iteration ratio."""
+    import torch
+
+    import paper_1503_03492_amd as smre
+    import smre_inputs as gi
+    H = W = 512
+    I, x_true = gi.deblur_problem(H, W, seed=0, psf_sigma=4.0, noise_sigma=1.0)
+    Id = torch.from_numpy(I.astype(np.float32)).cuda()
+    K = 4
+    r2 = smre.chi2_bounds([1 << k for k in range(K + 1)])
+    ctx = smre.Context(0)
+    kw = dict(method=smre.ADMM_ICD, K=K, radius2_icd=r2, icd_tol=1e-3, icd_mode=smre.TOL_MEANABS,
+              icd_max_inner=10000, delta=-1.0)
+    for _ in range(args.warmup):
+        ctx.admm(Id, 4.0, max_iter=5, **kw)
+    torch.cuda.synchronize()
+    reps, el = [], 0.0
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        x, rep = ctx.admm(Id, 4.0, max_iter=100, **kw)
+        torch.cuda.synchronize()
+        el += time.perf_counter() - t0
+        reps.append(rep)
+    xe = x.double().cpu().numpy()
+    sides = list(range(1, 16))
+    t0 = time.perf_counter()
+    _, frep = ctx.admm(Id, 4.0, method=smre.ADMM_FULL, sides=sides,
+                       radius2=smre.chi2_bounds(sides), full_tol=1e-3, full_max_sweeps=100000,
+                       delta=-1.0, max_iter=args.admm_exact_iters)
+    torch.cuda.synchronize()
+    t_exact = time.perf_counter() - t0
+    ms_iter = el / args.steps / 100 * 1e3
+    out = {"metric": "ADMM iterations/s (512^2 deblurring, ICD projection)",
+           "value": 100 * args.steps / el, "unit": "ADMM iterations/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic (piecewise-smooth scene, PSF 4 px, noise 1 gray level)",
+           "config": {"workload": "admm100_512sq_psf4_icdK4_tol1e-3", "H": H, "W": W,
+                      "iterations_per_step": 100, "K": K},
+           "ms_per_iteration": ms_iter,
+           "projection_share": sum(r["projection_ms"] for r in reps) / (el * 1e3),
+           "icd_inner_sweeps_per_iteration": reps[-1]["projection_sweeps"] / 100,
+           "last_dx": reps[-1]["last_dx"], "last_residual": reps[-1]["last_residual"],
+           "rel_error_to_scene": float(np.linalg.norm(xe - x_true) / np.linalg.norm(x_true)),
+           "exact": {"iterations": frep["iterations"], "ms_per_iteration":
+                     t_exact * 1e3 / frep["iterations"],
+                     "sweeps_per_iteration": frep["projection_sweeps"] / frep["iterations"],
+                     "icd_speedup_per_iteration": t_exact / frep["iterations"] / (ms_iter / 1e3)},
+           "roofline": None}
+    print(json.dumps(out), flush=True)
+
+
 def bench_full_vs_icd(args):
     """512^2 emitter image (200 emitters): full Dykstra (sides 1..8, FP32, tol
     1e-5) against the incomplete Dykstra (K = 3: squares of side 1, 2, 4, 8;
@@ -520,6 +578,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c3")
+    ap.add_argument("--admm-exact-iters", type=int, default=3,
+                    help="admm workload: iterations with the exact projection")
     ap.add_argument("--frames", type=int, default=3091,
                     help="sofi workload: frames of the movie")
     ap.add_argument("--mc-fields", type=int, default=4096,
@@ -555,6 +615,8 @@ def main():
         return bench_mc(args)
     if args.workload == "sofi":
         return bench_sofi(args)
+    if args.workload == "admm":
+        return bench_admm(args)
 
     import torch
 

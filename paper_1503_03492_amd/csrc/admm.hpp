@@ -48,12 +48,15 @@ __global__ __launch_bounds__(256) void blur_rows(const T* __restrict__ in, T* __
 }
 
 // Column pass: out[i][j] = sum_k w[|k|] in[i + k][j], zero outside the
-// column.  A block owns 64 columns x 64 rows of outputs; the 64 + 2R input
-// rows of those columns sit in LDS (loads and stores coalesced along rows).
+// column.  A block owns 64 columns x kBlurColRows rows of outputs (short
+// tiles, so a 512^2 image still gives 256 workgroups); the kBlurColRows + 2R
+// input rows of those columns sit in LDS (loads and stores coalesced along
+// rows).
+constexpr int kBlurColRows = 16;
 template <typename T>
 __global__ __launch_bounds__(256) void blur_cols(const T* __restrict__ in, T* __restrict__ out,
                                                  int H, int W, int64_t ld, PsfWeights pw) {
-  constexpr int TC = 64, TR = 64;
+  constexpr int TC = 64, TR = kBlurColRows;
   __shared__ T tile[TR + 2 * kAdmmMaxRadius][TC];
   const int R = pw.R, i0 = blockIdx.y * TR, j0 = blockIdx.x * TC;
   const int c = threadIdx.x & 63, g = threadIdx.x >> 6;

@@ -1658,7 +1658,8 @@ template <typename T>
 int blur(const T* in, T* tmp, T* out, int H, int W, const PsfWeights& pw, hipStream_t s) {
   hipLaunchKernelGGL((blur_rows<T>), dim3((W + 255) / 256, H), dim3(256), 0, s, in, tmp, H, W,
                      (int64_t)W, pw);
-  hipLaunchKernelGGL((blur_cols<T>), dim3((W + 63) / 64, (H + 63) / 64), dim3(256), 0, s, tmp,
+  hipLaunchKernelGGL((blur_cols<T>), dim3((W + 63) / 64, (H + kBlurColRows - 1) / kBlurColRows),
+                     dim3(256), 0, s, tmp,
                      out, H, W, (int64_t)W, pw);
   HIP_OK(hipGetLastError());
   return SMRE_OK;

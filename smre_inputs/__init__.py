@@ -146,3 +146,33 @@ def blinking_movie(n_frames, H, W, n_e=None, seed=0, mean_count=50.0, psf_sigma=
     if sd > 0:
         out /= dtype(sd) if dtype != np.float64 else sd
     return out
+
+
+def test_scene(H, W, seed=0, n_shapes=40):
+    """Piecewise-smooth gray-level scene (0..255): a smooth background
+    gradient plus random filled ellipses and rectangles of random gray levels,
+    standing in for a natural test image."""
+    rng = rng_for(seed)
+    yy, xx = np.meshgrid(np.arange(H) / max(H - 1, 1), np.arange(W) / max(W - 1, 1),
+                         indexing="ij")
+    img = 60.0 + 60.0 * yy + 40.0 * xx
+    for _ in range(n_shapes):
+        cy, cx = rng.uniform(0, 1, size=2)
+        ry, rx = rng.uniform(0.03, 0.25, size=2)
+        level = rng.uniform(0, 255)
+        if rng.random() < 0.5:
+            mask = ((yy - cy) / ry) ** 2 + ((xx - cx) / rx) ** 2 <= 1.0
+        else:
+            mask = (np.abs(yy - cy) <= ry) & (np.abs(xx - cx) <= rx)
+        img[mask] = level
+    return np.clip(img, 0.0, 255.0)
+
+
+def deblur_problem(H, W, seed=0, psf_sigma=4.0, noise_sigma=1.0):
+    """(I, x_true): the scene blurred by a Gaussian PSF (zero outside the
+    image) plus N(0, noise_sigma^2) noise, both divided by noise_sigma so the
+    noise has unit variance."""
+    x = test_scene(H, W, seed=seed)
+    blurred = gaussian_filter(x, psf_sigma, mode="constant", truncate=4.0)
+    noise = rng_for(seed + 1).standard_normal((H, W)) * noise_sigma
+    return (blurred + noise) / noise_sigma, x / noise_sigma
