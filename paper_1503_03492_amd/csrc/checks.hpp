@@ -21,6 +21,13 @@ __host__ __device__ inline double dkey_inv(unsigned long long k) {
   return d;
 }
 
+// atomicMax of a key that skips the atomic when the stored key is already at
+// least as large (a stale read only costs an unneeded atomic): with many
+// blocks reporting into one address most of them then skip it.
+__device__ __forceinline__ void key_max(unsigned long long* addr, unsigned long long k) {
+  if (k > __hip_atomic_load(addr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(addr, k);
+}
+
 struct Ctrl {
   int done;            // converged flag read by every sweep kernel
   int done_sweep;      // sweep at which it converged
@@ -63,7 +70,7 @@ __global__ __launch_bounds__(256) void delta_kernel(const TX* x, int64_t ld, int
     for (int col = threadIdx.x; col < W; col += blockDim.x)
       m = fmax(m, fabs((double)x[(int64_t)r * ld + col] - (double)prev[(int64_t)r * W + col]));
   m = block_max<TX>(m);
-  if (threadIdx.x == 0) atomicMax(&ctrl->delta_key, dkey(m));
+  if (threadIdx.x == 0) key_max(&ctrl->delta_key, dkey(m));
 }
 
 __global__ void decide_kernel(Ctrl* ctrl, double tol, int sweep) {
@@ -131,13 +138,7 @@ __global__ __launch_bounds__(256) void violation_kernel(const TX* x, int64_t fst
     m = fmax(m, n / r2 - 1.0);
   }
   m = block_max<TX>(m);
-  if (threadIdx.x == 0) {
-    // skip the atomic when the running maximum is already at least m (a stale
-    // read only costs an unneeded atomic): over many frames most blocks do
-    const unsigned long long k = dkey(m);
-    if (k > __hip_atomic_load(&ctrl->viol_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-      atomicMax(&ctrl->viol_key, k);
-  }
+  if (threadIdx.x == 0) key_max(&ctrl->viol_key, dkey(m));
 }
 
 template <typename T>
@@ -184,7 +185,7 @@ __global__ __launch_bounds__(256) void delta_batch(const ImageDesc* __restrict__
     for (int col = threadIdx.x; col < a.W; col += blockDim.x)
       m = fmax(m, fabs((double)x[(int64_t)r * a.ld + col] - (double)pv[(int64_t)r * a.W + col]));
   m = block_max<TX>(m);
-  if (threadIdx.x == 0) atomicMax(&ctl[im].delta_key, dkey(m));
+  if (threadIdx.x == 0) key_max(&ctl[im].delta_key, dkey(m));
 }
 
 // One block: close the sweep for every image (check and/or sweep cap) and
