@@ -360,6 +360,19 @@ def bench_sofi(args):
     x = torch.empty_like(d)
     ctx = smre.Context(0)
     ctx.set_timing(True)
+    if args.profile_sweeps > 0:
+        # counter-collection mode: the 1 GiB copy that calibrates FETCH_SIZE /
+        # WRITE_SIZE, then one pass over the movie; no timing line
+        a = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        x.copy_(d)
+        rep = ctx.incomplete_frames(x, K, r2, tol=1e-3, mode=smre.TOL_MEANABS, max_inner=10000)
+        print(json.dumps({"frames": n, "bytes_per_phase": rep["bytes_moved"] / (K + 1)}),
+              flush=True)
+        return
     for _ in range(args.warmup):
         x.copy_(d)
         ctx.incomplete_frames(x, K, r2, tol=1e-3, mode=smre.TOL_MEANABS, max_inner=10000)

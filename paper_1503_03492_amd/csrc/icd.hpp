@@ -75,6 +75,31 @@ constexpr int kIcdSlots = 256, kIcdSlotWords = 16;
 // MEANABS: stop when the block's sum of |dx| over an inner sweep is at most
 // tol times its pixel count (accumulated per lane in T, summed over the wave
 // in FP64); else when max |dx| < tol.
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2) in
+// dispatch order.  A block of 2^K FP32 pixels per row uses part of each
+// 128-byte line it touches and its horizontal neighbour uses the rest, so the
+// dispatch id is mapped to the block such that each XCD gets runs of 16
+// consecutive blocks (row-major over (x, y, frame)), the runs dealt to the
+// XCDs in turn: neighbours inside a run share an L2 instead of fetching the
+// same lines twice, and every XCD still samples the whole grid (frames of a
+// movie differ in how many inner sweeps their blocks need).  A bijection on
+// the grid (ids past the last whole group of 128 map to themselves); 32-bit
+// arithmetic, the host keeps a launch below 2^31 blocks.
+__device__ __forceinline__ void icd_block_of(unsigned& bx, unsigned& by, unsigned& bz) {
+  const unsigned nx = gridDim.x, nxy = gridDim.x * gridDim.y;
+  const unsigned total = nxy * gridDim.z;
+  const unsigned pid = blockIdx.z * nxy + blockIdx.y * nx + blockIdx.x;
+  unsigned lid = pid;
+  if (pid < (total & ~127u)) {
+    const unsigned xcd = pid & 7u, slot = pid >> 3;
+    lid = (((slot >> 4) << 3) + xcd) * 16u + (slot & 15u);
+  }
+  bz = lid / nxy;
+  const unsigned r = lid - bz * nxy;
+  by = r / nx;
+  bx = r - by * nx;
+}
+
 template <typename T, int K, bool MEANABS>
 __global__ __launch_bounds__(64) void icd_phase(IcdArgs a) {
   constexpr int B = 1 << K;
@@ -82,9 +107,11 @@ __global__ __launch_bounds__(64) void icd_phase(IcdArgs a) {
   constexpr int NPL = NPX >= 64 ? NPX / 64 : 1;
   const int lane = threadIdx.x;
   const int i = a.lmin;
-  const int by = (a.oy > 0 ? a.oy - B : 0) + (int)blockIdx.y * B;
-  const int bx = (a.ox > 0 ? a.ox - B : 0) + (int)blockIdx.x * B;
-  T* xg = (T*)a.x + (int64_t)blockIdx.z * a.fstride;
+  unsigned tx, ty, tz;
+  icd_block_of(tx, ty, tz);
+  const int by = (a.oy > 0 ? a.oy - B : 0) + (int)ty * B;
+  const int bx = (a.ox > 0 ? a.ox - B : 0) + (int)tx * B;
+  T* xg = (T*)a.x + (int64_t)tz * a.fstride;
 
   T x[NPL];
   bool inimg[NPL];

@@ -585,8 +585,11 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t fra
     int slot;
     rc = timing_begin(c, tacc, s, &slot);
     if (rc) return rc;
-    for (int64_t f0 = 0; f0 < frames; f0 += 65535) {
-      const dim3 grid(nbx, nby, (unsigned)std::min<int64_t>(65535, frames - f0));
+    // frames per launch: at most 65535 and fewer than 2^31 blocks in all
+    const int64_t fchunk = std::max<int64_t>(
+        1, std::min<int64_t>(65535, ((int64_t)1 << 31) / ((int64_t)nbx * nby) - 1));
+    for (int64_t f0 = 0; f0 < frames; f0 += fchunk) {
+      const dim3 grid(nbx, nby, (unsigned)std::min<int64_t>(fchunk, frames - f0));
       a.x = (T*)x + f0 * H * ld;
       if (mode == SMRE_TOL_MEANABS)
         launch_icd<T, true>(K, grid, a, s);
@@ -1951,6 +1954,11 @@ int smre_dykstra_incomplete_family(smre_ctx* c, smre_dtype dt, void* x, int64_t 
   if (dt != SMRE_F32 && dt != SMRE_F64) return SMRE_EINVAL;
   if (H < 1 || W < 1 || ld < W || H > (1 << 20) || W > (1 << 20)) return SMRE_EINVAL;
   if (K < 0 || K > 5 || max_inner < 1 || n_phases < 1 || n_phases > 64) return SMRE_EINVAL;
+  {
+    // blocks of one frame: within the grid limits and below 2^31 per launch
+    const int64_t nbx = W / (1 << K) + 2, nby = H / (1 << K) + 2;
+    if (nby > 65535 || nbx * nby >= ((int64_t)1 << 31)) return SMRE_EINVAL;
+  }
   for (int p = 0; p < n_phases; ++p)
     if (shift_y[p] < 0 || shift_y[p] >= (1 << K) || shift_x[p] < 0 || shift_x[p] >= (1 << K) ||
         min_level[p] < 0 || min_level[p] > K)
