@@ -55,3 +55,38 @@ def test_host_paper_bounds():
     import paper_1503_03492_amd as m
     # q = 0: bound = mu^4 = n - 1/2
     np.testing.assert_allclose(m.paper_bounds([1, 2, 4], 0.0), [0.5, 3.5, 15.5], rtol=1e-14)
+
+
+def test_header_is_plain_c_and_links(tmp_path):
+    """A C program compiles against include/smre.h (C11, no C++ or HIP types
+    in the signatures), links against the library and calls the host-only
+    helpers (no device needed)."""
+    import subprocess
+
+    import paper_1503_03492_amd as m
+    src = tmp_path / "use_abi.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include "smre.h"
+int main(void) {
+  int32_t sides[3] = {1, 2, 4};
+  double r2[3];
+  if (smre_chi2_bounds(sides, 3, 0.9, r2) != SMRE_OK) return 1;
+  if (smre_paper_bounds(sides, 3, 0.0, r2) != SMRE_OK) return 2;
+  if (r2[0] < 0.5 - 1e-14 || r2[0] > 0.5 + 1e-14) return 3;  /* (0.5^(1/4))^4 */
+  if (smre_dykstra_project(NULL, SMRE_F32, NULL, 1, 1, 1, NULL, NULL, 0, NULL, NULL) !=
+      SMRE_EINVAL) return 4;
+  if (smre_admm(NULL, SMRE_F32, NULL, NULL, 1, 1, 1, NULL, NULL, NULL, NULL) != SMRE_EINVAL)
+    return 5;
+  printf("%s\n", smre_status_string(SMRE_ENONFINITE));
+  return 0;
+}
+''')
+    exe = tmp_path / "use_abi"
+    libdir = os.path.dirname(m.LIB_PATH)
+    subprocess.check_call(["gcc", "-std=c11", "-Wall", "-Werror", "-I",
+                           os.path.join(ROOT, "include"), str(src), "-o", str(exe), "-L", libdir,
+                           "-lsmre", f"-Wl,-rpath,{libdir}"])
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0, (out.returncode, out.stderr)
+    assert "non-finite" in out.stdout
