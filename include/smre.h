@@ -161,7 +161,8 @@ int smre_dykstra_incomplete(smre_ctx* ctx, smre_dtype dtype, void* x, int64_t H,
  * H ld elements apart from x (device), each projected in place exactly as
  * smre_dykstra_incomplete would project it alone; every phase is one launch
  * over all frames.  frames * H <= 2^31 - 1.  report: inner_sweeps, window and
- * pixel counts summed over frames; max_violation over all frames. */
+ * pixel counts summed over frames; max_violation over all frames (report may be
+ * NULL: the feasibility pass behind max_violation is then skipped). */
 int smre_dykstra_incomplete_frames(smre_ctx* ctx, smre_dtype dtype, void* x, int64_t H,
                                    int64_t W, int64_t ld, int64_t frames, int32_t K,
                                    const double* radius2, double tol, int32_t tolmode,

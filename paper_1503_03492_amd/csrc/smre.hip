@@ -614,7 +614,7 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t fra
   // exact method: the largest window sum of each (frame, side) from the
   // all-sides tile kernel, then the worst ratio to its bound.
   double viol = NAN;
-  if (checks) {
+  if (checks && rep) {  // the feasibility pass only feeds the report
     std::vector<int32_t> fam;
     std::vector<double> fam_r2;
     for (int k = 0; k <= K; ++k)

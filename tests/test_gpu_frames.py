@@ -179,3 +179,22 @@ def test_family_rejects_bad_phases(ctx, smre):
         ctx.incomplete_family(x, 2, bounds(2), [(0, 0, 3)])
     with pytest.raises(smre.SmreError):
         ctx.incomplete_family(x, 2, bounds(2), [])
+
+
+def test_frames_without_report_same_result(ctx, smre):
+    # through the C ABI with report = NULL (the feasibility pass is skipped):
+    # the frames come out bitwise as with a report
+    import ctypes
+    n, H, W, K = 3, 48, 64, 4
+    movie = gi.blinking_movie(n, H, W, n_e=8, seed=12)
+    r2 = np.ascontiguousarray(bounds(K))
+    a = torch.from_numpy(movie).cuda()
+    b = a.clone()
+    ctx.incomplete_frames(a, K, r2, tol=1e-3, mode=1)
+    rc = smre.lib().smre_dykstra_incomplete_frames(
+        ctx._h, smre.F32, ctypes.c_void_p(b.data_ptr()), H, W, W, n, K,
+        r2.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 1e-3, 1, 10000, K + 1,
+        ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), None)
+    torch.cuda.synchronize()
+    assert rc == 0
+    assert torch.equal(a, b)
