@@ -75,7 +75,7 @@ def workload(name):
     if name == "c3bf16":
         return dict(workload="dykstra_1024sq_sides1-16_fp32_bf16inc", H=1024, W=1024, n_e=2000,
                     sides=list(range(1, 17)), dtype="fp32", tol=1e-5, max_sweeps=5000,
-                    inc="bf16")
+                    inc="bf16", profile="region_phase_1024sq_sides1-16_bf16inc.md")
     if name == "c2":
         return dict(workload="dykstra_512sq_sides1-8_fp32", H=512, W=512, n_e=200,
                     sides=list(range(1, 9)), dtype="fp32", tol=1e-5, max_sweeps=5000,
