@@ -40,6 +40,10 @@ def lib():
                                      ctypes.c_int32, ctypes.c_double, ctypes.c_int32, dp, dp,
                                      ip, dp]
         L.oracle_dykstra.restype = ctypes.c_int
+        L.oracle_dykstra_warm.argtypes = L.oracle_dykstra.argtypes
+        L.oracle_dykstra_warm.restype = ctypes.c_int
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_threads.restype = ctypes.c_int
         L.oracle_window_count.argtypes = [i64, i64, ip, ctypes.c_int32]
         L.oracle_window_count.restype = i64
         L.oracle_max_violation.argtypes = [dp, i64, i64, ip, ctypes.c_int32, dp]
@@ -97,12 +101,23 @@ def ntilings(sides):
     return int(sum(int(s) * int(s) for s in sides))
 
 
+def set_threads(n):
+    """Worker threads of the sweeps (1 = sequential).  Every count gives
+    bitwise the same iterates (the threads take disjoint windows / regions).
+    Returns the count in effect."""
+    return lib().oracle_set_threads(int(n))
+
+
 def dykstra(x0, sides, r2, tol=1e-10, max_sweeps=500, order=ORDER_DESC, region=0,
-            want_incs=False):
+            want_incs=False, incs0=None, in_place=False):
     """Full Dykstra in FP64.  Returns (z, sweeps, last_delta[, incs]).
 
     tol <= 0 runs exactly max_sweeps sweeps.  incs has shape (T, H, W) with
     tilings indexed sides-descending, then offset row a, then offset column b.
+    incs0 (same shape) starts Dykstra from those increments instead of zero
+    (x starts at x0 - sum_S I_S); it is not modified unless in_place is set
+    (then it must be a C-contiguous float64 array and receives the final
+    increments, which saves a copy of a large state).
     """
     x0 = np.ascontiguousarray(x0, dtype=np.float64)
     H, W = x0.shape
@@ -110,14 +125,23 @@ def dykstra(x0, sides, r2, tol=1e-10, max_sweeps=500, order=ORDER_DESC, region=0
     r2 = np.ascontiguousarray(r2, dtype=np.float64)
     z = np.empty_like(x0)
     incs = None
-    if want_incs:
+    if incs0 is not None and in_place:
+        if incs0.dtype != np.float64 or not incs0.flags.c_contiguous:
+            raise ValueError("in_place needs a C-contiguous float64 incs0")
+        incs = incs0
+    elif incs0 is not None:
+        incs = np.array(incs0, dtype=np.float64, order="C", copy=True)
+    if incs0 is not None:
+        if incs.shape != (ntilings(sides), H, W):
+            raise ValueError("incs0 must have shape (T, H, W)")
+    elif want_incs:
         incs = np.empty((ntilings(sides), H, W), dtype=np.float64)
     sw = ctypes.c_int32(0)
     dl = ctypes.c_double(0)
-    rc = lib().oracle_dykstra(_d(x0), H, W, _i(sides), len(sides), _d(r2), int(order),
-                              int(region), float(tol), int(max_sweeps), _d(z),
-                              _d(incs) if incs is not None else None, ctypes.byref(sw),
-                              ctypes.byref(dl))
+    fn = lib().oracle_dykstra_warm if incs0 is not None else lib().oracle_dykstra
+    rc = fn(_d(x0), H, W, _i(sides), len(sides), _d(r2), int(order), int(region), float(tol),
+            int(max_sweeps), _d(z), _d(incs) if incs is not None else None, ctypes.byref(sw),
+            ctypes.byref(dl))
     if rc != 0:
         raise ValueError("oracle_dykstra rejected its arguments")
     if want_incs:

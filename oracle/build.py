@@ -1,4 +1,5 @@
-"""Build the oracle shared library (plain C, gcc, IEEE double, no contraction).
+"""Build the oracle shared library (plain C, gcc, IEEE double, no contraction;
+OpenMP for the optional multi-threaded sweeps, one thread by default).
 
 Test infrastructure only: the HIP library never links or loads this.
 """
@@ -13,7 +14,7 @@ LIB = os.path.join(HERE, "libsmre_oracle.so")
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fPIC",
-           "-shared", "-o", LIB, SRC, "-lm"]
+           "-shared", "-fopenmp", "-o", LIB, SRC, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -37,8 +37,10 @@
  * input), KKT certificate, variational inequality, brute-force QCQP, symmetry,
  * nonexpansiveness, order independence, chi-square closed forms vs SciPy.
  */
+#define _DEFAULT_SOURCE /* madvise */
 #include <math.h>
 #include <stdint.h>
+#include <sys/mman.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -218,6 +220,22 @@ static void project_tiling_part(double* x, double* inc, int64_t H, int64_t W, in
     for (int64_t j = j0; j < jhi; j += s) project_window(x, inc, W, i, j, s, r2, ybuf);
 }
 
+/* Worker threads for the sweeps (1: plain sequential loops).  Windows of one
+ * tiling are disjoint, and so are the footprints of the regions of one colour
+ * in the region order, so the work split between threads touches disjoint
+ * pixels and increments: every thread count gives bitwise the same iterates. */
+static int g_threads = 1;
+
+int oracle_set_threads(int n) {
+#ifdef _OPENMP
+  g_threads = n < 1 ? 1 : n;
+#else
+  (void)n;
+  g_threads = 1;
+#endif
+  return g_threads;
+}
+
 /*
  * One Dykstra sweep visits every window of the family once (Algorithm 2).
  * Windows of one tiling (s, a, b) -- the squares [a+s p, a+s p+s) x [b+s q, ...)
@@ -235,9 +253,27 @@ static void project_tiling_part(double* x, double* inc, int64_t H, int64_t W, in
  * R >= smax - 1 two regions of one colour touch disjoint pixels, so the order
  * of regions within a colour is immaterial as well.
  */
+static void sweep_region(double* x, double* incs, int64_t H, int64_t W, const side_table* st,
+                         int64_t R, int64_t p, int64_t q, double* ybuf) {
+  int64_t HW = H * W;
+  for (int k = 0; k < st->n; ++k) {
+    int32_t s = st->side[k];
+    for (int32_t ap = 0; ap < s; ++ap)
+      for (int32_t bp = 0; bp < s; ++bp) {
+        /* offsets (ap, bp) count from the region origin */
+        int32_t a = (int32_t)((p * R + ap) % s), b = (int32_t)((q * R + bp) % s);
+        double* inc = incs + (st->tbase[k] + (int64_t)a * s + b) * HW;
+        project_tiling_part(x, inc, H, W, s, a, b, st->r2[k], p * R, p * R + R, q * R,
+                            q * R + R, ybuf);
+      }
+  }
+}
+
 static void sweep(double* x, double* incs, int64_t H, int64_t W, const side_table* st, int order,
                   int32_t region, double* ybuf) {
   int64_t HW = H * W;
+  const int nt = g_threads;
+  const size_t ybytes = (size_t)st->side[0] * st->side[0] * sizeof(double);
   if (order == ORACLE_ORDER_DESC || order == ORACLE_ORDER_ASC) {
     for (int kk = 0; kk < st->n; ++kk) {
       int k = (order == ORACLE_ORDER_DESC) ? kk : st->n - 1 - kk;
@@ -245,61 +281,114 @@ static void sweep(double* x, double* incs, int64_t H, int64_t W, const side_tabl
       for (int32_t a = 0; a < s; ++a)
         for (int32_t b = 0; b < s; ++b) {
           double* inc = incs + (st->tbase[k] + (int64_t)a * s + b) * HW;
-          project_tiling_part(x, inc, H, W, s, a, b, st->r2[k], 0, H, 0, W, ybuf);
+          if (nt == 1) {
+            project_tiling_part(x, inc, H, W, s, a, b, st->r2[k], 0, H, 0, W, ybuf);
+            continue;
+          }
+          /* one band of window rows per iteration: disjoint windows */
+          int64_t nrows = (H - a) / s;
+#pragma omp parallel num_threads(nt)
+          {
+            double* yb = (double*)malloc(ybytes);
+#pragma omp for schedule(static)
+            for (int64_t r = 0; r < nrows; ++r)
+              project_tiling_part(x, inc, H, W, s, a, b, st->r2[k], a + r * s, a + r * s + 1, 0,
+                                  W, yb);
+            free(yb);
+          }
         }
     }
     return;
   }
   int64_t R = region;
   int64_t nry = (H + R - 1) / R, nrx = (W + R - 1) / R;
-  for (int color = 0; color < 4; ++color)
-    for (int64_t p = color >> 1; p < nry; p += 2)
-      for (int64_t q = color & 1; q < nrx; q += 2)
-        for (int k = 0; k < st->n; ++k) {
-          int32_t s = st->side[k];
-          for (int32_t ap = 0; ap < s; ++ap)
-            for (int32_t bp = 0; bp < s; ++bp) {
-              /* offsets (ap, bp) count from the region origin */
-              int32_t a = (int32_t)((p * R + ap) % s), b = (int32_t)((q * R + bp) % s);
-              double* inc = incs + (st->tbase[k] + (int64_t)a * s + b) * HW;
-              project_tiling_part(x, inc, H, W, s, a, b, st->r2[k], p * R, p * R + R, q * R,
-                                  q * R + R, ybuf);
-            }
-        }
+  for (int color = 0; color < 4; ++color) {
+    if (nt == 1) {
+      for (int64_t p = color >> 1; p < nry; p += 2)
+        for (int64_t q = color & 1; q < nrx; q += 2)
+          sweep_region(x, incs, H, W, st, R, p, q, ybuf);
+      continue;
+    }
+    /* the regions of one colour have disjoint footprints */
+    int64_t npy = (nry - (color >> 1) + 1) / 2, npx = (nrx - (color & 1) + 1) / 2;
+#pragma omp parallel num_threads(nt)
+    {
+      double* yb = (double*)malloc(ybytes);
+#pragma omp for schedule(dynamic, 4)
+      for (int64_t r = 0; r < npy * npx; ++r)
+        sweep_region(x, incs, H, W, st, R, (color >> 1) + 2 * (r / npx),
+                     (color & 1) + 2 * (r % npx), yb);
+      free(yb);
+    }
+  }
 }
 
-/*
- * Dykstra projection of x0 onto the intersection of the window balls.
- *   x0, z      : H x W row-major (z may alias a copy of x0; x0 is not written)
- *   sides, r2  : nsides window sides and their bounds (sum of squares <= r2)
- *   order      : ORACLE_ORDER_*; region: R for ORACLE_ORDER_REGION
- *   tol        : stop after the first sweep with max|x - x_prev| < tol
- *                (tol <= 0: run exactly max_sweeps sweeps)
- *   incs       : optional T x H x W increments I (canonical tiling index:
- *                sides descending, then a, then b); zero-initialised here.
- * Returns 0, or -1 on invalid arguments / allocation failure.
- */
-int oracle_dykstra(const double* x0, int64_t H, int64_t W, const int32_t* sides, int32_t nsides,
-                   const double* r2, int32_t order, int32_t region, double tol,
-                   int32_t max_sweeps, double* z, double* incs, int32_t* sweeps_out,
-                   double* delta_out) {
+/* Sum over every window S of the family of its increment I_S at each pixel
+ * (canonical tiling layout; entries of a tiling plane outside its windows are
+ * ignored). */
+static void increment_sum(const double* incs, int64_t H, int64_t W, const side_table* st,
+                          double* acc) {
+  int64_t HW = H * W;
+  memset(acc, 0, (size_t)HW * sizeof(double));
+  for (int k = 0; k < st->n; ++k) {
+    int32_t s = st->side[k];
+    for (int32_t a = 0; a < s; ++a)
+      for (int32_t b = 0; b < s; ++b) {
+        const double* inc = incs + (st->tbase[k] + (int64_t)a * s + b) * HW;
+        for (int64_t i0 = a; i0 + s <= H; i0 += s)
+          for (int64_t j0 = b; j0 + s <= W; j0 += s)
+            for (int64_t i = i0; i < i0 + s; ++i)
+              for (int64_t j = j0; j < j0 + s; ++j) acc[i * W + j] += inc[i * W + j];
+      }
+  }
+}
+
+/* Large buffers (the increments: T H W doubles) on 2 MiB boundaries with
+ * transparent huge pages requested: a region touches a few rows of every
+ * tiling plane, which with 4 KiB pages costs a TLB miss per row. */
+static double* alloc_big(size_t n) {
+  void* p = NULL;
+  size_t bytes = n * sizeof(double);
+  if (posix_memalign(&p, (size_t)2 << 20, bytes ? bytes : 1) != 0) return NULL;
+#ifdef MADV_HUGEPAGE
+  madvise(p, bytes, MADV_HUGEPAGE);
+#endif
+  return (double*)p;
+}
+
+static int dykstra_run(const double* x0, int64_t H, int64_t W, const int32_t* sides,
+                       int32_t nsides, const double* r2, int32_t order, int32_t region,
+                       double tol, int32_t max_sweeps, double* z, double* incs, int warm,
+                       int32_t* sweeps_out, double* delta_out) {
   side_table st;
   if (H < 1 || W < 1 || max_sweeps < 1) return -1;
   if (make_side_table(sides, r2, nsides, H, W, &st) != 0) return -1;
   if (order == ORACLE_ORDER_REGION && (region < 1 || region < st.side[0] - 1)) return -1;
   if (order < 0 || order > 2) return -1;
+  if (warm && !incs) return -1;
   int64_t HW = H * W;
   int own = 0;
   if (!incs) {
-    incs = (double*)malloc((size_t)(st.ntilings * HW) * sizeof(double));
+    incs = alloc_big((size_t)(st.ntilings * HW));
     if (!incs) return -1;
     own = 1;
   }
-  memset(incs, 0, (size_t)(st.ntilings * HW) * sizeof(double));
   double* prev = (double*)malloc((size_t)HW * sizeof(double));
   double* ybuf = (double*)malloc((size_t)st.side[0] * st.side[0] * sizeof(double));
   if (!prev || !ybuf) { free(prev); free(ybuf); if (own) free(incs); return -1; }
-  if (z != x0) memcpy(z, x0, (size_t)HW * sizeof(double));
+  if (warm) {
+    /* Dykstra's invariant x + sum_S I_S = x0 fixes the start from given
+     * increments: x = x0 - sum_S I_S. */
+    increment_sum(incs, H, W, &st, prev);
+#if ORACLE_MUTANT == 10
+    for (int64_t i = 0; i < HW; ++i) z[i] = x0[i]; /* start ignores the given increments */
+#else
+    for (int64_t i = 0; i < HW; ++i) z[i] = x0[i] - prev[i];
+#endif
+  } else {
+    memset(incs, 0, (size_t)(st.ntilings * HW) * sizeof(double));
+    if (z != x0) memcpy(z, x0, (size_t)HW * sizeof(double));
+  }
   int32_t sw = 0;
   double delta = INFINITY;
   while (sw < max_sweeps) {
@@ -319,6 +408,43 @@ int oracle_dykstra(const double* x0, int64_t H, int64_t W, const int32_t* sides,
   free(ybuf);
   if (own) free(incs);
   return 0;
+}
+
+/*
+ * Dykstra projection of x0 onto the intersection of the window balls.
+ *   x0, z      : H x W row-major (z may alias a copy of x0; x0 is not written)
+ *   sides, r2  : nsides window sides and their bounds (sum of squares <= r2)
+ *   order      : ORACLE_ORDER_*; region: R for ORACLE_ORDER_REGION
+ *   tol        : stop after the first sweep with max|x - x_prev| < tol
+ *                (tol <= 0: run exactly max_sweeps sweeps)
+ *   incs       : optional T x H x W increments I (canonical tiling index:
+ *                sides descending, then a, then b); zero-initialised here.
+ * Returns 0, or -1 on invalid arguments / allocation failure.
+ */
+int oracle_dykstra(const double* x0, int64_t H, int64_t W, const int32_t* sides, int32_t nsides,
+                   const double* r2, int32_t order, int32_t region, double tol,
+                   int32_t max_sweeps, double* z, double* incs, int32_t* sweeps_out,
+                   double* delta_out) {
+  return dykstra_run(x0, H, W, sides, nsides, r2, order, region, tol, max_sweeps, z, incs, 0,
+                     sweeps_out, delta_out);
+}
+
+/*
+ * Dykstra started from given increments (a warm start, e.g. from the
+ * projection of a nearby input, as when Algorithm 1 projects a slowly changing
+ * point every iteration).  Dykstra is block-coordinate minimisation of the
+ * dual function of the projection, so it reaches the same limit from any
+ * increments; the iterate starts at x = x0 - sum_S I_S so that the invariant
+ * x + sum_S I_S = x0 holds from the first window on.  incs (T x H x W,
+ * canonical layout, required) holds the start on entry and the final
+ * increments on return; other arguments as oracle_dykstra.
+ */
+int oracle_dykstra_warm(const double* x0, int64_t H, int64_t W, const int32_t* sides,
+                        int32_t nsides, const double* r2, int32_t order, int32_t region,
+                        double tol, int32_t max_sweeps, double* z, double* incs,
+                        int32_t* sweeps_out, double* delta_out) {
+  return dykstra_run(x0, H, W, sides, nsides, r2, order, region, tol, max_sweeps, z, incs, 1,
+                     sweeps_out, delta_out);
 }
 
 /* Number of windows of the family (each side: (H-s+1)(W-s+1)). */

@@ -275,3 +275,107 @@ def test_pins_catch_planted_mistakes(tmp_path, mutant):
     caught_bf = not np.allclose(z, ref, atol=1e-6)
     caught_feas = oracle.max_violation(z, sides, r2) > 1e-9
     assert caught_bf or caught_feas
+
+
+# ---------------------------------------------------------------- threads
+
+@pytest.mark.parametrize("order,region", [(oracle.ORDER_DESC, 0), (oracle.ORDER_ASC, 0),
+                                          (oracle.ORDER_REGION, 8), (oracle.ORDER_REGION, 16)])
+def test_threads_bitwise_equal(order, region):
+    """The threaded sweeps split disjoint windows (one tiling) or disjoint region
+    footprints (one colour): every thread count gives the same bits."""
+    sides = [1, 2, 3, 5, 8]
+    r2 = bounds(sides)
+    x0 = gi.emitters(70, 83, n_e=12, seed=21)
+    try:
+        oracle.set_threads(1)
+        a, sa, da, ia = oracle.dykstra(x0, sides, r2, tol=0, max_sweeps=6, order=order,
+                                       region=region, want_incs=True)
+        assert oracle.set_threads(4) == 4
+        b, sb, db, ib = oracle.dykstra(x0, sides, r2, tol=0, max_sweeps=6, order=order,
+                                       region=region, want_incs=True)
+    finally:
+        oracle.set_threads(1)
+    assert np.array_equal(a, b) and np.array_equal(ia, ib) and da == db
+
+
+# ---------------------------------------------------------------- warm start
+
+def _converged(x0, sides, r2, **kw):
+    return oracle.dykstra(x0, sides, r2, tol=1e-13, max_sweeps=50000, want_incs=True, **kw)
+
+
+def test_warm_start_from_own_limit_stops_at_once():
+    """Started from the converged increments of the same input, Dykstra starts at
+    x0 - sum_S I_S = z (the invariant) and the first sweep changes nothing."""
+    sides = [1, 2, 3, 5]
+    r2 = bounds(sides)
+    x0 = gi.noise_blob(23, 19, seed=2)
+    z, _, d, incs = _converged(x0, sides, r2)
+    assert d < 1e-13
+    z2, sw, d2 = oracle.dykstra(x0, sides, r2, tol=1e-12, max_sweeps=100, incs0=incs)
+    assert sw == 1 and d2 < 1e-12
+    assert np.max(np.abs(z2 - z)) <= 1e-12
+
+
+@pytest.mark.parametrize("order,region", [(oracle.ORDER_DESC, 0), (oracle.ORDER_REGION, 8)])
+def test_warm_start_from_arbitrary_increments_reaches_projection(order, region):
+    """Dykstra is block-coordinate minimisation of the dual of the projection, so
+    any start reaches the same limit; the final state passes the KKT
+    certificate and the invariant holds after every sweep."""
+    sides = [1, 2, 3, 5]
+    r2 = bounds(sides)
+    x0 = gi.emitters(24, 29, n_e=4, seed=3)
+    ref, _, _, _ = _converged(x0, sides, r2)
+    rng = np.random.default_rng(7)
+    T = oracle.ntilings(sides)
+    inc0 = rng.normal(scale=0.5, size=(T,) + x0.shape)
+    z1, _, _, i1 = oracle.dykstra(x0, sides, r2, tol=0, max_sweeps=3, order=order,
+                                  region=region, incs0=inc0, want_incs=True)
+    assert oracle.kkt(x0, z1, i1, sides, r2)["sum_invariant"] <= 1e-12
+    z, sw, d, incs = oracle.dykstra(x0, sides, r2, tol=1e-13, max_sweeps=100000, order=order,
+                                    region=region, incs0=inc0, want_incs=True)
+    assert d < 1e-13
+    assert np.max(np.abs(z - ref)) <= 1e-10
+    c = oracle.kkt(x0, z, incs, sides, r2, slack=1e-7)
+    assert c["max_violation"] <= 1e-9 and c["sum_invariant"] <= 1e-12
+    assert c["mult_residual"] <= 1e-9 and c["mu_min"] >= -1e-12 and c["inactive_inc"] <= 1e-9
+
+
+def test_warm_start_from_nearby_input_takes_fewer_sweeps():
+    """Projecting a slightly moved input from the increments of the first
+    projection (the situation of Algorithm 1's repeated projections) reaches
+    the cold-start limit in fewer sweeps."""
+    sides = [1, 2, 3, 4, 6]
+    r2 = bounds(sides)
+    x0 = gi.emitters(32, 36, n_e=6, seed=5)
+    _, _, _, incs = oracle.dykstra(x0, sides, r2, tol=1e-10, max_sweeps=50000, want_incs=True)
+    x1 = x0 + 0.01 * gi.gaussian(32, 36, seed=6)
+    cold, sc, _ = oracle.dykstra(x1, sides, r2, tol=1e-10, max_sweeps=50000)
+    warm, sw, _ = oracle.dykstra(x1, sides, r2, tol=1e-10, max_sweeps=50000, incs0=incs)
+    assert sw < sc
+    assert np.max(np.abs(warm - cold)) <= 1e-8
+
+
+def test_warm_start_mutant_caught(tmp_path):
+    """A warm start that keeps x = x0 (ignoring the given increments) converges
+    to the projection of a different point; the same-limit pin catches it."""
+    so = str(tmp_path / "mut10.so")
+    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-std=c11", "-fPIC", "-shared",
+                           "-DORACLE_MUTANT=10", "-o", so,
+                           os.path.join(os.path.dirname(oracle.__file__), "smre_oracle.c"),
+                           "-lm"])
+    L = ctypes.CDLL(so)
+    L.oracle_dykstra_warm.argtypes = oracle.lib().oracle_dykstra_warm.argtypes
+    sides = np.array([1, 2, 3], dtype=np.int32)
+    r2 = bounds(sides)
+    x0 = gi.emitters(12, 14, n_e=3, seed=8)
+    ref, _, _ = oracle.dykstra(x0, sides, r2, tol=1e-13, max_sweeps=50000)
+    inc = np.random.default_rng(1).normal(scale=0.5, size=(oracle.ntilings(sides), 12, 14))
+    z = np.empty_like(x0)
+    sw, dl = ctypes.c_int32(0), ctypes.c_double(0)
+    rc = L.oracle_dykstra_warm(oracle._d(x0), 12, 14, oracle._i(sides), 3, oracle._d(r2), 0, 0,
+                               1e-13, 50000, oracle._d(z), oracle._d(inc), ctypes.byref(sw),
+                               ctypes.byref(dl))
+    assert rc == 0
+    assert np.max(np.abs(z - ref)) > 1e-6
