@@ -149,7 +149,10 @@ int smre_dykstra_project(smre_ctx* ctx, smre_dtype dtype, void* x, int64_t H, in
  *   num_phases    phases i = 0..num_phases-1 (1..K+1; the paper's family: K+1)
  * Phase i: blocks on the lattice shifted by 2^i mod 2^K on both axes; a block
  * projects onto its squares of side 2^k, k = K down to i, with increments
- * zeroed at the start of the phase. */
+ * zeroed at the start of the phase.
+ * Returns SMRE_OK, SMRE_NOT_CONVERGED (the result is written, but at least one
+ * block stopped at max_inner without meeting tol; report->converged = 0), or
+ * an error. */
 int smre_dykstra_incomplete(smre_ctx* ctx, smre_dtype dtype, void* x, int64_t H, int64_t W,
                             int64_t ld, int32_t K, const double* radius2, double tol,
                             int32_t tolmode, int32_t max_inner, int32_t num_phases, void* stream,

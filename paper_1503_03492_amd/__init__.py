@@ -318,7 +318,7 @@ class Context:
                                           H, W, ld, int(K), rp, float(tol), int(mode),
                                           int(max_inner), int(num_phases), _stream(stream),
                                           ctypes.byref(rep))
-        _check(rc, "smre_dykstra_incomplete")
+        _check(rc, "smre_dykstra_incomplete", allow=(OK, NOT_CONVERGED))
         return rep.as_dict()
 
     def incomplete_frames(self, x, K, radius2, tol=1e-3, mode=TOL_MEANABS, max_inner=10000,
@@ -342,7 +342,7 @@ class Context:
                                                  n, int(K), rp, float(tol), int(mode),
                                                  int(max_inner), int(num_phases), _stream(stream),
                                                  ctypes.byref(rep))
-        _check(rc, "smre_dykstra_incomplete_frames")
+        _check(rc, "smre_dykstra_incomplete_frames", allow=(OK, NOT_CONVERGED))
         return rep.as_dict()
 
     def incomplete_family(self, x, K, radius2, phases, tol=1e-3, mode=TOL_MEANABS,
@@ -370,7 +370,7 @@ class Context:
                                                  int(K), rp, len(sy), syp, sxp, lop, float(tol),
                                                  int(mode), int(max_inner), _stream(stream),
                                                  ctypes.byref(rep))
-        _check(rc, "smre_dykstra_incomplete_family")
+        _check(rc, "smre_dykstra_incomplete_family", allow=(OK, NOT_CONVERGED))
         return rep.as_dict()
 
     def project_batch(self, xs, sides, radius2, tol=1e-5, max_sweeps=5000, region=0,

@@ -32,7 +32,7 @@ struct Ctrl {
   int done;            // converged flag read by every sweep kernel
   int done_sweep;      // sweep at which it converged
   int nonfinite;       // input check result
-  int pad;
+  int abort;           // a sweep kernel's producer/consumer wait gave up
   unsigned long long delta_key;  // running max |x - prev| of the checked sweep
   double last_delta;
   unsigned long long viol_key;   // running max violation
@@ -152,6 +152,7 @@ __global__ void ctrl_reset_kernel(Ctrl* c) {
   c->done = 0;
   c->done_sweep = 0;
   c->nonfinite = 0;
+  c->abort = 0;
   c->delta_key = dkey(0.0);
   c->last_delta = -1.0;
   c->viol_key = dkey(-1.0);
@@ -209,7 +210,7 @@ __global__ __launch_bounds__(256) void decide_batch(BatchCtl* ctl, int n, int ch
         stop = true;
       }
     }
-    if (sw >= c.max_sweeps) stop = true;
+    if (sw >= c.max_sweeps || c.aborted) stop = true;
     if (stop) {
       c.done = 1;
       c.done_sweep = sw;

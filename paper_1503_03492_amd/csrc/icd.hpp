@@ -173,6 +173,7 @@ __global__ __launch_bounds__(64) void icd_phase(IcdArgs a) {
     for (int e = 0; e < NPL; ++e) q[k][e] = T(0);
 
   int it = 0;
+  bool met = false;  // the stopping rule held (else the block hit max_inner)
   while (true) {
     T dsum = T(0), dmax = T(0);
 #pragma unroll
@@ -236,6 +237,7 @@ __global__ __launch_bounds__(64) void icd_phase(IcdArgs a) {
     } else {
       stop = (double)wave_max(dmax) < a.tol;
     }
+    met = stop;
     if (stop || it >= a.max_inner) break;
   }
 #pragma unroll
@@ -247,6 +249,7 @@ __global__ __launch_bounds__(64) void icd_phase(IcdArgs a) {
     atomicAdd(c + 0, (unsigned long long)it);
     atomicAdd(c + 1, (unsigned long long)it * (unsigned long long)(nsq + 0.5f));
     atomicAdd(c + 2, (unsigned long long)it * (unsigned long long)(nunit + 0.5f));
+    if (!met) atomicAdd(c + 3, 1ull);  // stopped by the cap
   }
 }
 

@@ -339,7 +339,7 @@ struct BatchCtl {
   int sweeps;                    // sweeps this image has run (images may join at different times)
   int check_every;
   int gen;                       // occupant generation (serving: tells a slot's requests apart)
-  int pad;
+  int aborted;                   // a region job of this image hit a wait bound (device error)
   unsigned long long delta_key;  // running max |x - prev| of the checked sweep
   double last_delta;
   double tol;
@@ -628,10 +628,6 @@ template <typename TX, typename TQ, int R, int SMAX> struct PhaseLds {
   int ctr[3];  // pages ready, pages consumed, abort flag
 };
 
-// Set when a wait inside a region job gave up (a protocol failure, reported
-// as a device error by the host).
-__device__ int g_wait_abort;
-
 // One region of one image: both waves of the workgroup enter; the caller
 // resets the counters and synchronises the workgroup before and after.
 template <typename TX, typename TQ, int R, int SMAX, bool KAHAN>
@@ -717,30 +713,35 @@ __device__ __forceinline__ void reset_counters(PhaseLds<TX, TQ, R, SMAX>& L) {
   __syncthreads();
 }
 
+// A wait inside the region job gave up (a protocol failure): raise the
+// caller's flag -- the single-image call's control block or the image's
+// batch control block -- which the host reports as a device error for that
+// solve only.
 template <typename TX, typename TQ, int R, int SMAX>
-__device__ __forceinline__ void report_abort(PhaseLds<TX, TQ, R, SMAX>& L) {
+__device__ __forceinline__ void report_abort(PhaseLds<TX, TQ, R, SMAX>& L, int* flag) {
   __syncthreads();
-  if (threadIdx.x == 0 && L.ctr[2]) atomicOr(&g_wait_abort, 1);
+  if (threadIdx.x == 0 && L.ctr[2]) atomicOr(flag, 1);
 }
 
 // One image, one colour: block b takes the b-th region of colour (cy, cx).
 template <typename TX, typename TQ, int R, int SMAX, bool KAHAN>
 __global__ __launch_bounds__(128) void region_phase(ImageDesc a, int cy, int cx, int ncx,
-                                                    const int* done, unsigned char* q) {
+                                                    const int* done, int* abort_flag,
+                                                    unsigned char* q) {
   __shared__ PhaseLds<TX, TQ, R, SMAX> L;
   if (*done) return;
   const int b = blockIdx.x;
   const int region = (cy + 2 * (b / ncx)) * a.nrx + cx + 2 * (b % ncx);
   reset_counters(L);
   region_job<TX, TQ, R, SMAX, KAHAN>(a, region, q, L);
-  report_abort(L);
+  report_abort(L, abort_flag);
 }
 
 // A batch of images, one colour: a persistent grid walks the colour's work
 // list; items of converged images are skipped.
 template <typename TX, typename TQ, int R, int SMAX, bool KAHAN>
 __global__ __launch_bounds__(128) void region_phase_batch(const ImageDesc* __restrict__ imgs,
-                                                          const BatchCtl* __restrict__ ctl,
+                                                          BatchCtl* __restrict__ ctl,
                                                           const WorkItem* __restrict__ items,
                                                           const int* __restrict__ nitems,
                                                           unsigned char* q) {
@@ -751,7 +752,7 @@ __global__ __launch_bounds__(128) void region_phase_batch(const ImageDesc* __res
     if (ctl[w.img].done) continue;
     reset_counters(L);
     region_job<TX, TQ, R, SMAX, KAHAN>(imgs[w.img], w.region, q, L);
-    report_abort(L);
+    report_abort(L, &ctl[w.img].aborted);
   }
 }
 

@@ -48,6 +48,7 @@ struct Request {
   std::vector<float> out;       // result, filled at retirement
   smre_report rep{};
   int status = SMRE_PENDING;    // PENDING until retired
+  int failed_alone = 0;         // set by retire: this request's result is bad (its status)
   double t_submit = 0, t_admit = 0, t_done = 0;
   int slot = -1;
 };
@@ -65,7 +66,9 @@ class Backend {
   // One sweep over all admitted slots; appends the slots found finished.
   // An error fails the whole server.
   virtual int step(std::vector<int>& finished) = 0;
-  // Copy the result of slot s into r (out, rep) and free the slot.
+  // Copy the result of slot s into r (out, rep) and free the slot.  An error
+  // return fails the whole server; a failure of this request alone is
+  // reported through r.failed_alone.
   virtual int retire(Request& r, int s) = 0;
 };
 
@@ -242,7 +245,9 @@ class Server {
           used_ = 0;
           break;
         }
-        finish(*r, r->rep.converged || r->tol <= 0 ? SMRE_OK : SMRE_NOT_CONVERGED);
+        finish(*r, r->failed_alone ? r->failed_alone
+                                   : r->rep.converged || r->tol <= 0 ? SMRE_OK
+                                                                     : SMRE_NOT_CONVERGED);
         slot_req_[s] = nullptr;
         used_ -= r->footprint;
         --active_;

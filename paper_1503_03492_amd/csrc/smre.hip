@@ -198,16 +198,6 @@ void build_round_tables(const Plan& pl, int64_t H, int64_t W, size_t es, RoundEn
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// A sweep kernel whose producer/consumer wait gave up sets g_wait_abort (a
-// protocol failure: the results are not trustworthy).
-int check_wait_abort(hipStream_t s) {
-  int v = 0;
-  HIP_OK(hipMemcpyFromSymbolAsync(&v, HIP_SYMBOL(g_wait_abort), sizeof v, 0,
-                                  hipMemcpyDeviceToHost, s));
-  HIP_OK(hipStreamSynchronize(s));
-  return v ? SMRE_EDEVICE : SMRE_OK;
-}
-
 int choose_region(int smax, int requested) {
   if (requested) return requested;
   if (smax <= 17) return 16;
@@ -337,6 +327,7 @@ int grid_rows(int64_t H) { return (int)std::max<int64_t>(1, std::min<int64_t>(40
 struct PhaseLaunch {
   int cy, cx, ncx, blocks;
   const int* done;
+  int* abort;  // raised by a region job whose producer/consumer wait gave up
   unsigned char* q;
 };
 
@@ -344,7 +335,7 @@ template <typename TX, typename TQ, int R, bool KAHAN>
 void launch_phase(const ImageDesc& a, const PhaseLaunch& l, hipStream_t s) {
   constexpr int SMAX = R + 1;
   hipLaunchKernelGGL((region_phase<TX, TQ, R, SMAX, KAHAN>), dim3(l.blocks), dim3(128), 0, s, a,
-                     l.cy, l.cx, l.ncx, l.done, l.q);
+                     l.cy, l.cx, l.ncx, l.done, l.abort, l.q);
 }
 
 template <typename TX, typename TQ, bool KAHAN>
@@ -461,6 +452,7 @@ int project_impl(smre_ctx* c, smre_dtype dt, void* x, int64_t H, int64_t W, int6
       l.ncx = nx;
       l.blocks = ny * nx;
       l.done = &c->ctrl->done;
+      l.abort = &c->ctrl->abort;
       l.q = ws;
       if (ny <= 0 || nx <= 0) continue;
       int slot;
@@ -500,7 +492,8 @@ int project_impl(smre_ctx* c, smre_dtype dt, void* x, int64_t H, int64_t W, int6
   if (rc) return rc;
   HIP_OK(hipEventRecord(c->t1, s));
   HIP_OK(hipEventSynchronize(c->t1));
-  if ((rc = check_wait_abort(s))) return rc;
+  // a wait that gave up is a protocol failure: the result is not trustworthy
+  if (fin.abort) return SMRE_EDEVICE;
   float ms = 0.f;
   HIP_OK(hipEventElapsedTime(&ms, c->t0, c->t1));
   if (rep) {
@@ -606,9 +599,11 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t fra
   std::vector<unsigned long long> slots((size_t)kCntWords);
   HIP_OK(hipMemcpy(slots.data(), c->icd_cnt, sizeof(unsigned long long) * kCntWords,
                    hipMemcpyDeviceToHost));
-  unsigned long long cnt[3] = {0, 0, 0};
+  // inner sweeps, square projections, (square, pixel) updates, blocks that
+  // stopped at max_inner without meeting the tolerance
+  unsigned long long cnt[4] = {0, 0, 0, 0};
   for (int k = 0; k < kIcdSlots; ++k)
-    for (int w = 0; w < 3; ++w) cnt[w] += slots[(size_t)k * kIcdSlotWords + w];
+    for (int w = 0; w < 4; ++w) cnt[w] += slots[(size_t)k * kIcdSlotWords + w];
   // Reported: the violation over the FULL family of the levels' sides (every
   // position, every frame), i.e. how far ICD is from feasibility for the
   // exact method: the largest window sum of each (frame, side) from the
@@ -641,7 +636,7 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t fra
   HIP_OK(hipEventElapsedTime(&ms, c->t0, c->t1));
   if (rep) {
     rep->sweeps = nph;
-    rep->converged = 1;
+    rep->converged = cnt[3] == 0;
     rep->region = B;
     rep->inner_sweeps = (int32_t)std::min<unsigned long long>(cnt[0], INT32_MAX);
     rep->last_delta = NAN;
@@ -653,7 +648,7 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t fra
     rep->window_projections = (double)cnt[1];
     rep->pixel_updates = (double)cnt[2];
   }
-  return SMRE_OK;
+  return cnt[3] == 0 ? SMRE_OK : SMRE_NOT_CONVERGED;
 }
 
 // ---------------------------------------------------------------- batches
@@ -727,7 +722,7 @@ int batch_grid(int cus, int want) {
 }
 
 template <typename TX, typename TQ, bool KAHAN>
-int launch_batch_phase(int R, int grid, const ImageDesc* d, const BatchCtl* ctl,
+int launch_batch_phase(int R, int grid, const ImageDesc* d, BatchCtl* ctl,
                        const WorkItem* items, const int* cnt, unsigned char* q, hipStream_t s) {
   switch (R) {
     case 8:
@@ -1058,9 +1053,10 @@ int batch_impl(smre_ctx* c, smre_dtype dt, int n, const smre_batch_image* im,
     if (gx[g]) (void)hipGraphExecDestroy(gx[g]);
     if (gr[g]) (void)hipGraphDestroy(gr[g]);
   }
-  if ((rc = check_wait_abort(s))) return rc;
   std::vector<BatchCtl> ctl(n);
   HIP_OK(hipMemcpy(ctl.data(), D.ctl, sizeof(BatchCtl) * n, hipMemcpyDeviceToHost));
+  for (int i = 0; i < n; ++i)
+    if (ctl[i].aborted) return SMRE_EDEVICE;  // a wait gave up: results not trustworthy
   HIP_OK(hipEventRecord(c->t1, s));
   HIP_OK(hipEventSynchronize(c->t1));
   float ms = 0.f;
@@ -1346,8 +1342,10 @@ class HipBackend : public smre_serve::Backend {
     HIP_OK(hipMemcpyAsync(r.out.data(), sl.desc.x, r.out.size() * sizeof(float),
                           hipMemcpyDeviceToHost, stream_));
     HIP_OK(hipStreamSynchronize(stream_));
-    if (int rc = check_wait_abort(stream_)) return rc;
     std::memset(&r.rep, 0, sizeof r.rep);
+    // a wait of one of this request's region jobs gave up: its result alone
+    // is not trustworthy
+    if (sl.last.aborted) r.failed_alone = SMRE_EDEVICE;
     r.rep.sweeps = sl.last.done_sweep;
     r.rep.converged = sl.last.converged;
     r.rep.region = 16;
@@ -1746,7 +1744,7 @@ int admm_impl(smre_ctx* c, smre_dtype dt, const T* I_user, T* x_user, int64_t H,
     if (p->method == SMRE_ADMM_ICD) {
       rc = icd_impl<T>(c, eps, H, W, W, 1, p->K, p->radius2_icd, p->icd_tol, p->icd_tolmode,
                        p->icd_max_inner, p->K + 1, sy, sx, lo, s, &pr, false);
-      if (rc) return rc;
+      if (rc != SMRE_OK && rc != SMRE_NOT_CONVERGED) return rc;  // a capped block is fine here
       psweeps += pr.inner_sweeps;
     } else {
       rc = smre_dykstra_project(c, dt, eps, H, W, W, p->full, nullptr, 0, s, &pr);

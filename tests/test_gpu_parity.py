@@ -346,3 +346,19 @@ def test_icd_paper_mode_runs_close(ctx):
     # same stopping rule; the decision may flip only on rounding-level ties
     assert relerr(x.cpu().numpy(), ref) <= 1e-3
     assert rep["inner_sweeps"] == pytest.approx(n_ref, rel=0.01)
+
+
+def test_icd_cap_reported_not_converged(ctx, smre):
+    """Blocks stopped by max_inner are counted: the report says not converged
+    (and the C call returns NOT_CONVERGED); with room to converge it says 1."""
+    H, W, K = 64, 64, 3
+    x0 = gi.emitters(H, W, n_e=10, seed=13)
+    r2 = oracle.chi2_bounds([1 << k for k in range(K + 1)])
+    x = dev(x0)
+    rep = ctx.incomplete(x, K, r2, tol=1e-13, mode=0, max_inner=1)
+    assert rep["converged"] == 0
+    ref, _ = oracle.icd(x0, K, r2, tol=1e-13, mode=oracle.TOL_MAXABS, max_inner=1)
+    assert relerr(x.cpu().numpy(), ref) <= 1e-12
+    x = dev(x0)
+    rep = ctx.incomplete(x, K, r2, tol=1e-13, mode=0, max_inner=100000)
+    assert rep["converged"] == 1
