@@ -70,6 +70,17 @@ typedef struct smre_ctx smre_ctx;
  *                     (0 = choose; else 8, 16 or 32 with R >= max side - 1)
  *   inc               increment storage (FP32 x only for SMRE_INC_BF16)
  *   kahan             FP32: compensated per-lane window sums (0/1)
+ *   warm              0: start from zero increments.  1: start from the
+ *                     increments the previous smre_dykstra_project call left
+ *                     in this workspace (same dtype, H, W, sides, bounds,
+ *                     region and increment storage; SMRE_EINVAL otherwise,
+ *                     also after a call that failed): Dykstra from any
+ *                     increments reaches the same limit (it minimises the
+ *                     dual function block by block), so a slowly moving
+ *                     input -- the eps-step of Algorithm 1 -- needs fewer
+ *                     sweeps.  x holds the new input x0; the iterate starts at
+ *                     x0 - sum_S I_S, with sum_S I_S = x0_prev - z_prev kept
+ *                     from the previous call (Dykstra's invariant)
  *   guard_rel         FP32: windows with |n - r2| <= guard_rel * r2 are
  *                     re-summed in FP64 before the threshold test (0 = off)
  *
@@ -92,7 +103,7 @@ typedef struct {
   int32_t region;
   int32_t inc;
   int32_t kahan;
-  int32_t reserved0;
+  int32_t warm;
   double guard_rel;
 } smre_params;
 
@@ -352,7 +363,8 @@ typedef struct {
   int32_t icd_tolmode;
   double icd_tol;
   int32_t icd_max_inner;
-  int32_t reserved;
+  int32_t warm;          /* full projection: 1 = every eps-step after the first
+                            starts from the previous one's increments */
   const double* radius2_icd;
   /* full projection: sides, radius2, tol, max_sweeps, ... (smre_params) */
   const smre_params* full;

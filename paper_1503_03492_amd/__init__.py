@@ -33,7 +33,7 @@ class Params(ctypes.Structure):
                 ("radius2", ctypes.POINTER(ctypes.c_double)), ("tol", ctypes.c_double),
                 ("max_sweeps", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("region", ctypes.c_int32), ("inc", ctypes.c_int32), ("kahan", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("guard_rel", ctypes.c_double)]
+                ("warm", ctypes.c_int32), ("guard_rel", ctypes.c_double)]
 
 
 class Report(ctypes.Structure):
@@ -82,7 +82,7 @@ class AdmmParams(ctypes.Structure):
                 ("delta", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("method", ctypes.c_int32), ("K", ctypes.c_int32),
                 ("icd_tolmode", ctypes.c_int32), ("icd_tol", ctypes.c_double),
-                ("icd_max_inner", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("icd_max_inner", ctypes.c_int32), ("warm", ctypes.c_int32),
                 ("radius2_icd", ctypes.POINTER(ctypes.c_double)),
                 ("full", ctypes.POINTER(Params))]
 
@@ -243,6 +243,9 @@ class ProjectOptions:
     inc: int = INC_SAME
     kahan: bool = True
     guard_rel: float = 1e-5
+    # start from the increments the previous call on the same problem left in
+    # the workspace (the context's cached one, or the one passed)
+    warm: bool = False
 
 
 class Context:
@@ -275,7 +278,8 @@ class Context:
         if len(s) != len(r):
             raise ValueError("sides and radius2 differ in length")
         p = Params(len(s), sp, rp, float(o.tol), int(o.max_sweeps), int(o.check_every),
-                   int(o.region), int(o.inc), 1 if o.kahan else 0, 0, float(o.guard_rel))
+                   int(o.region), int(o.inc), 1 if o.kahan else 0, 1 if o.warm else 0,
+                   float(o.guard_rel))
         return p, (s, r)
 
     def workspace_size(self, dtype, H, W, sides, radius2, opts=None):
@@ -422,7 +426,8 @@ class Context:
     def admm(self, I, sigma, method=ADMM_ICD, K=4, radius2_icd=None, icd_tol=1e-3,
              icd_mode=TOL_MEANABS, icd_max_inner=10000, sides=None, radius2=None, full_tol=1e-5,
              full_max_sweeps=5000, lam=1.0, rho1=6.192, rho2=1.8, alpha1=1.2, alpha2=0.12,
-             gamma=0.0, delta=1e-3, max_iter=100, want_eps=False, stream=None):
+             gamma=0.0, delta=1e-3, max_iter=100, want_eps=False, full_warm=False,
+             stream=None):
         """ADMM estimate x (new tensor like I) for the data I (2-D CUDA tensor);
         returns (x, report) or (x, eps, report)."""
         import torch
@@ -433,7 +438,8 @@ class Context:
         keep = []
         p = AdmmParams(float(sigma), float(lam), float(rho1), float(rho2), float(alpha1),
                        float(alpha2), float(gamma), float(delta), int(max_iter), int(method),
-                       int(K), int(icd_mode), float(icd_tol), int(icd_max_inner), 0, None, None)
+                       int(K), int(icd_mode), float(icd_tol), int(icd_max_inner),
+                       1 if full_warm else 0, None, None)
         if method == ADMM_ICD:
             r, rp = _dvec(radius2_icd)
             keep.append(r)

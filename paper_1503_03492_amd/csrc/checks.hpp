@@ -148,6 +148,39 @@ __global__ __launch_bounds__(256) void fill_kernel(T* p, int64_t n, T v) {
     p[i] = v;
 }
 
+// Warm start (Dykstra's invariant x + sum_S I_S = x0): isum holds the
+// previous solve's sum_S I_S = x0_prev - z_prev; the new input x0 in x is
+// kept in isum and the iterate starts at x0 - sum_S I_S.
+template <typename TX>
+__global__ __launch_bounds__(256) void warm_begin_kernel(TX* x, int64_t ld, int H, int W,
+                                                         TX* isum) {
+  for (int r = blockIdx.x; r < H; r += gridDim.x)
+    for (int col = threadIdx.x; col < W; col += blockDim.x) {
+      const TX v = x[(int64_t)r * ld + col];
+      TX& s = isum[(int64_t)r * W + col];
+      x[(int64_t)r * ld + col] = v - s;
+      s = v;
+    }
+}
+
+// Cold start: keep the input x0 in isum.
+template <typename TX>
+__global__ __launch_bounds__(256) void keep_input_kernel(const TX* x, int64_t ld, int H, int W,
+                                                         TX* isum) {
+  for (int r = blockIdx.x; r < H; r += gridDim.x)
+    for (int col = threadIdx.x; col < W; col += blockDim.x)
+      isum[(int64_t)r * W + col] = x[(int64_t)r * ld + col];
+}
+
+// End of a solve: isum = x0 - z = sum_S I_S, the start of the next warm solve.
+template <typename TX>
+__global__ __launch_bounds__(256) void increment_sum_kernel(const TX* x, int64_t ld, int H,
+                                                            int W, TX* isum) {
+  for (int r = blockIdx.x; r < H; r += gridDim.x)
+    for (int col = threadIdx.x; col < W; col += blockDim.x)
+      isum[(int64_t)r * W + col] -= x[(int64_t)r * ld + col];
+}
+
 __global__ void ctrl_reset_kernel(Ctrl* c) {
   c->done = 0;
   c->done_sweep = 0;

@@ -71,6 +71,26 @@ struct IcdArgs {
   unsigned long long* counters;
 };
 constexpr int kIcdSlots = 256, kIcdSlotWords = 16;
+// Words per slot that the kernel adds to: inner sweeps, square projections,
+// (square, pixel) updates, blocks stopped by max_inner.
+constexpr int kIcdCountWords = 4;
+
+// One block of kIcdSlots threads: out[w] = sum over the slots of word w.
+__global__ __launch_bounds__(kIcdSlots) void icd_counter_sum(const unsigned long long* cnt,
+                                                             unsigned long long* out) {
+  __shared__ unsigned long long red[kIcdCountWords][kIcdSlots];
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int w = 0; w < kIcdCountWords; ++w) red[w][t] = cnt[(size_t)t * kIcdSlotWords + w];
+  __syncthreads();
+  for (int h = kIcdSlots / 2; h > 0; h >>= 1) {
+    if (t < h)
+#pragma unroll
+      for (int w = 0; w < kIcdCountWords; ++w) red[w][t] += red[w][t + h];
+    __syncthreads();
+  }
+  if (t < kIcdCountWords) out[t] = red[t][0];
+}
 
 // MEANABS: stop when the block's sum of |dx| over an inner sweep is at most
 // tol times its pixel count (accumulated per lane in T, summed over the wave

@@ -18,6 +18,8 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
+#include <optional>
 #include <string>
 #include <vector>
 
@@ -122,6 +124,7 @@ int timing_end(smre_ctx* c, TimingAcc& acc, hipStream_t s, int slot) {
 }
 
 // ---------------------------------------------------------------- planning
+constexpr int kSigWords = 8;
 struct Plan {
   int R = 16;
   int nsides = 0;
@@ -132,7 +135,7 @@ struct Plan {
   int64_t nq = 0;  // increment elements
   int64_t nwin = 0;
   size_t qbytes = 0;
-  size_t off_roff = 0, off_prev = 0, total = 0;
+  size_t off_roff = 0, off_prev = 0, off_isum = 0, off_sig = 0, total = 0;
   std::vector<RegionStream> roff;  // page layout of each region's increments
   // device metadata blob: the region streams, then (16-byte aligned) the round
   // tables; meta_bytes covers both whether or not the blob is built
@@ -213,6 +216,7 @@ int plan_project(smre_dtype dt, int64_t H, int64_t W, const smre_params* p, Plan
   if (p->max_sweeps < 1 || p->check_every < 1) return SMRE_EINVAL;
   if (p->inc != SMRE_INC_SAME && p->inc != SMRE_INC_BF16) return SMRE_EINVAL;
   if (p->inc == SMRE_INC_BF16 && dt != SMRE_F32) return SMRE_EINVAL;
+  if (p->warm != 0 && p->warm != 1) return SMRE_EINVAL;
   if (!std::isfinite(p->tol) || !std::isfinite(p->guard_rel) || p->guard_rel < 0)
     return SMRE_EINVAL;
   std::vector<std::pair<int, double>> sd;
@@ -297,8 +301,30 @@ int plan_project(smre_dtype dt, int64_t H, int64_t W, const smre_params* p, Plan
   }
   pl->off_roff = pl->qbytes;
   pl->off_prev = align_up(pl->off_roff + pl->meta_bytes, 256);
-  pl->total = align_up(pl->off_prev + (size_t)H * W * xs, 256);
+  pl->off_isum = align_up(pl->off_prev + (size_t)H * W * xs, 256);
+  pl->off_sig = align_up(pl->off_isum + (size_t)H * W * xs, 256);
+  pl->total = align_up(pl->off_sig + kSigWords * sizeof(uint64_t), 256);
   return SMRE_OK;
+}
+
+// What a workspace's increments belong to: written at the end of a solve,
+// cleared at the start of a cold one; a warm start requires a match.
+void problem_signature(smre_dtype dt, int64_t H, int64_t W, const smre_params* p,
+                       const Plan& pl, uint64_t* sig) {
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the sorted sides and bounds
+  auto mix = [&](const void* b, size_t n) {
+    for (size_t i = 0; i < n; ++i) h = (h ^ ((const unsigned char*)b)[i]) * 1099511628211ull;
+  };
+  mix(pl.sides, sizeof(int) * pl.nsides);
+  mix(pl.r2, sizeof(double) * pl.nsides);
+  sig[0] = 0x534d524557524d31ull;
+  sig[1] = (uint64_t)dt | ((uint64_t)p->inc << 8) | ((uint64_t)pl.R << 16);
+  sig[2] = (uint64_t)H;
+  sig[3] = (uint64_t)W;
+  sig[4] = h;
+  sig[5] = (uint64_t)pl.nq;
+  sig[6] = (uint64_t)pl.qbytes;
+  sig[7] = 0;
 }
 
 int ensure_ctrl(smre_ctx* c) {
@@ -406,10 +432,30 @@ int project_impl(smre_ctx* c, smre_dtype dt, void* x, int64_t H, int64_t W, int6
   if (rc) return rc;
   if (bad) return SMRE_ENONFINITE;
 
-  // increments start at zero (a fill kernel, not a memset: graph-safe)
-  const int64_t nwords = (int64_t)(pl.qbytes / 4);
-  hipLaunchKernelGGL((fill_kernel<uint32_t>), dim3(grid_for(nwords)), dim3(256), 0, s,
-                     (uint32_t*)ws, nwords, 0u);
+  uint64_t sig[kSigWords];
+  problem_signature(dt, H, W, p, pl, sig);
+  TX* isum = (TX*)(ws + pl.off_isum);
+  uint64_t* dsig = (uint64_t*)(ws + pl.off_sig);
+  if (p->warm) {
+    // the increments (and sum_S I_S) of the previous solve of this problem
+    uint64_t have[kSigWords];
+    HIP_OK(hipMemcpyAsync(have, dsig, sizeof have, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (std::memcmp(have, sig, sizeof sig) != 0) return SMRE_EINVAL;
+    hipLaunchKernelGGL((warm_begin_kernel<TX>), dim3(grid_rows(H)), dim3(256), 0, s, (TX*)x, ld,
+                       (int)H, (int)W, isum);
+  } else {
+    // increments start at zero (a fill kernel, not a memset: graph-safe)
+    const int64_t nwords = (int64_t)(pl.qbytes / 4);
+    hipLaunchKernelGGL((fill_kernel<uint32_t>), dim3(grid_for(nwords)), dim3(256), 0, s,
+                       (uint32_t*)ws, nwords, 0u);
+    hipLaunchKernelGGL((keep_input_kernel<TX>), dim3(grid_rows(H)), dim3(256), 0, s,
+                       (const TX*)x, ld, (int)H, (int)W, isum);
+  }
+  // until this solve ends, the workspace holds no reusable increments
+  hipLaunchKernelGGL((fill_kernel<uint64_t>), dim3(1), dim3(256), 0, s, dsig, (int64_t)kSigWords,
+                     (uint64_t)0);
+  HIP_OK(hipGetLastError());
   HIP_OK(hipMemcpyAsync(ws + pl.off_roff, pl.meta.data(), pl.meta.size(), hipMemcpyHostToDevice,
                         s));
 
@@ -481,12 +527,18 @@ int project_impl(smre_ctx* c, smre_dtype dt, void* x, int64_t H, int64_t W, int6
       }
     }
   }
+  // sum_S I_S = x0 - z for a later warm start
+  hipLaunchKernelGGL((increment_sum_kernel<TX>), dim3(grid_rows(H)), dim3(256), 0, s,
+                     (const TX*)x, ld, (int)H, (int)W, isum);
+  HIP_OK(hipGetLastError());
   HIP_OK(hipStreamSynchronize(s));
   rc = timing_flush(c, tacc, true);
   if (rc) return rc;
   HIP_OK(hipMemcpy(c->ctrl_host, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
   const Ctrl fin = *c->ctrl_host;
   const int sweeps_run = fin.done ? fin.done_sweep : p->max_sweeps;
+  if (!fin.abort)  // the increments belong to this problem now
+    HIP_OK(hipMemcpy(dsig, sig, sizeof sig, hipMemcpyHostToDevice));
   double viol = 0.0;
   rc = run_violation<TX>(c, x, H, W, ld, pl.nsides, pl.sides, pl.r2, s, &viol);
   if (rc) return rc;
@@ -530,16 +582,38 @@ template <bool GEN, typename T>
 int mc_run(smre_ctx* c, const T* fields, int64_t ld, int64_t H, int64_t W, uint64_t seed,
            int64_t f0, int64_t nf, const McSides& sd, double* q_out, double* tmax_out,
            hipStream_t s, TimingAcc& acc);
+template <bool GEN, typename T>
+int mc_run_buf(smre_ctx* c, const T* fields, int64_t ld, int64_t H, int64_t W, uint64_t seed,
+               int64_t f0, int64_t nf, const McSides& sd, double* q_out, double* tmax_out,
+               hipStream_t s, TimingAcc* acc, unsigned long long* tmax, double* q);
 int mc_sides(int32_t n, const int32_t* sides, int64_t H, int64_t W, McSides* sd);
 
-// Phase p: lattice shift (sy[p], sx[p]), levels K down to lo[p].
+// Device scratch of one ICD call: the work counters (kIcdSlots lines), their
+// sums, and for the single-frame feasibility report the per-level window
+// maxima and the statistic of the frame.
+struct IcdScratch {
+  unsigned long long* cnt;   // kIcdSlots * kIcdSlotWords words
+  unsigned long long* sum;   // kIcdCountWords words
+  unsigned long long* tmax;  // K + 1 words (one frame)
+  double* q;                 // one double
+};
+constexpr int64_t kIcdCntWords = (int64_t)kIcdSlots * kIcdSlotWords;
+// words of the allocation-free scratch: counters, sums, maxima (K + 1 <= 6,
+// rounded up), the statistic
+constexpr int64_t kIcdScratchWords = kIcdCntWords + 8 + 8 + 8;
+
+
+// Phase p: lattice shift (sy[p], sx[p]), levels K down to lo[p].  fixed:
+// caller-supplied device scratch (one frame; no allocation on any path, no
+// per-kernel timing); null: the context's buffers, allocated on first use.
 template <typename T>
 int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t frames, int K,
              const double* r2, double tol, int mode, int max_inner, int nph, const int32_t* sy,
              const int32_t* sx, const int32_t* lo, hipStream_t s, smre_report* rep,
-             bool checks = true) {
+             bool checks = true, const IcdScratch* fixed = nullptr) {
   // checks: the non-finite test of the input and the feasibility report (an
   // inner call of the ADMM loop, whose inputs are its own, skips both)
+  if (fixed && frames != 1) return SMRE_EINVAL;
   HIP_OK(hipEventRecord(c->t0, s));
   int rc = SMRE_OK;
   if (checks) {
@@ -550,10 +624,18 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t fra
     if (rc) return rc;
     if (bad) return SMRE_ENONFINITE;
   }
-  constexpr int64_t kCntWords = (int64_t)kIcdSlots * kIcdSlotWords;
-  if (!c->icd_cnt) HIP_OK(hipMalloc(&c->icd_cnt, sizeof(unsigned long long) * kCntWords));
-  hipLaunchKernelGGL((fill_kernel<unsigned long long>), dim3(grid_for(kCntWords)), dim3(256), 0,
-                     s, c->icd_cnt, kCntWords, 0ull);
+  unsigned long long *cnt, *cnt_sum;
+  if (fixed) {
+    cnt = fixed->cnt;
+    cnt_sum = fixed->sum;
+  } else {
+    if (!c->icd_cnt)
+      HIP_OK(hipMalloc(&c->icd_cnt, sizeof(unsigned long long) * (kIcdCntWords + 8)));
+    cnt = c->icd_cnt;
+    cnt_sum = c->icd_cnt + kIcdCntWords;
+  }
+  hipLaunchKernelGGL((fill_kernel<unsigned long long>), dim3(grid_for(kIcdCntWords)), dim3(256),
+                     0, s, cnt, kIcdCntWords, 0ull);
   IcdArgs a{};
   a.ld = ld;
   a.fstride = H * ld;
@@ -566,18 +648,18 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t fra
     a.r2[k] = r2[k];
     a.sr2[k] = std::sqrt((float)r2[k]);
   }
-  a.counters = c->icd_cnt;
+  a.counters = cnt;
   const int B = 1 << K;
-  TimingAcc tacc;
+  std::optional<TimingAcc> tacc;  // (its queue allocates: not on the fixed path)
+  if (!fixed) tacc.emplace();
   for (int ph = 0; ph < nph; ++ph) {
     a.oy = sy[ph];
     a.ox = sx[ph];
     a.lmin = lo[ph];
     const int start_y = sy[ph] > 0 ? sy[ph] - B : 0, start_x = sx[ph] > 0 ? sx[ph] - B : 0;
     const int nby = (int)((H - start_y + B - 1) / B), nbx = (int)((W - start_x + B - 1) / B);
-    int slot;
-    rc = timing_begin(c, tacc, s, &slot);
-    if (rc) return rc;
+    int slot = -1;
+    if (tacc && (rc = timing_begin(c, *tacc, s, &slot))) return rc;
     // frames per launch: at most 65535 and fewer than 2^31 blocks in all
     const int64_t fchunk = std::max<int64_t>(
         1, std::min<int64_t>(65535, ((int64_t)1 << 31) / ((int64_t)nbx * nby) - 1));
@@ -590,45 +672,50 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t fra
         launch_icd<T, false>(K, grid, a, s);
       HIP_OK(hipGetLastError());
     }
-    rc = timing_end(c, tacc, s, slot);
-    if (rc) return rc;
+    if (tacc && (rc = timing_end(c, *tacc, s, slot))) return rc;
   }
-  HIP_OK(hipStreamSynchronize(s));
-  rc = timing_flush(c, tacc, true);
-  if (rc) return rc;
-  std::vector<unsigned long long> slots((size_t)kCntWords);
-  HIP_OK(hipMemcpy(slots.data(), c->icd_cnt, sizeof(unsigned long long) * kCntWords,
-                   hipMemcpyDeviceToHost));
   // inner sweeps, square projections, (square, pixel) updates, blocks that
   // stopped at max_inner without meeting the tolerance
-  unsigned long long cnt[4] = {0, 0, 0, 0};
-  for (int k = 0; k < kIcdSlots; ++k)
-    for (int w = 0; w < 4; ++w) cnt[w] += slots[(size_t)k * kIcdSlotWords + w];
+  hipLaunchKernelGGL(icd_counter_sum, dim3(1), dim3(kIcdSlots), 0, s, cnt, cnt_sum);
+  HIP_OK(hipGetLastError());
+  unsigned long long sums[kIcdCountWords];
+  HIP_OK(hipMemcpyAsync(sums, cnt_sum, sizeof sums, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  if (tacc && (rc = timing_flush(c, *tacc, true))) return rc;
   // Reported: the violation over the FULL family of the levels' sides (every
   // position, every frame), i.e. how far ICD is from feasibility for the
   // exact method: the largest window sum of each (frame, side) from the
   // all-sides tile kernel, then the worst ratio to its bound.
   double viol = NAN;
   if (checks && rep) {  // the feasibility pass only feeds the report
-    std::vector<int32_t> fam;
-    std::vector<double> fam_r2;
+    int32_t fam[6];
+    double fam_r2[6];
+    int nfam = 0;
     for (int k = 0; k <= K; ++k)
       if ((1 << k) <= H && (1 << k) <= W) {
-        fam.push_back(1 << k);
-        fam_r2.push_back(r2[k]);
+        fam[nfam] = 1 << k;
+        fam_r2[nfam++] = r2[k];
       }
     McSides sd;
-    rc = mc_sides((int32_t)fam.size(), fam.data(), H, W, &sd);
-    if (rc) return rc;
-    std::vector<double> qf((size_t)frames), tmax((size_t)frames * fam.size());
-    TimingAcc vacc;
-    rc = mc_run<false, T>(c, (const T*)x, ld, H, W, 0, 0, frames, sd, qf.data(), tmax.data(), s,
-                          vacc);
+    rc = mc_sides(nfam, fam, H, W, &sd);
     if (rc) return rc;
     viol = -INFINITY;
-    for (int64_t f = 0; f < frames; ++f)
-      for (size_t k = 0; k < fam.size(); ++k)
-        viol = std::max(viol, tmax[(size_t)f * fam.size() + k] / fam_r2[k] - 1.0);
+    if (fixed) {
+      double q1 = 0.0, tm[6];
+      rc = mc_run_buf<false, T>(c, (const T*)x, ld, H, W, 0, 0, 1, sd, &q1, tm, s, nullptr,
+                                fixed->tmax, fixed->q);
+      if (rc) return rc;
+      for (int k = 0; k < nfam; ++k) viol = std::max(viol, tm[k] / fam_r2[k] - 1.0);
+    } else {
+      std::vector<double> qf((size_t)frames), tmax((size_t)frames * nfam);
+      TimingAcc vacc;
+      rc = mc_run<false, T>(c, (const T*)x, ld, H, W, 0, 0, frames, sd, qf.data(), tmax.data(),
+                            s, vacc);
+      if (rc) return rc;
+      for (int64_t f = 0; f < frames; ++f)
+        for (int k = 0; k < nfam; ++k)
+          viol = std::max(viol, tmax[(size_t)f * nfam + k] / fam_r2[k] - 1.0);
+    }
   }
   HIP_OK(hipEventRecord(c->t1, s));
   HIP_OK(hipEventSynchronize(c->t1));
@@ -636,19 +723,19 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t fra
   HIP_OK(hipEventElapsedTime(&ms, c->t0, c->t1));
   if (rep) {
     rep->sweeps = nph;
-    rep->converged = cnt[3] == 0;
+    rep->converged = sums[3] == 0;
     rep->region = B;
-    rep->inner_sweeps = (int32_t)std::min<unsigned long long>(cnt[0], INT32_MAX);
+    rep->inner_sweeps = (int32_t)std::min<unsigned long long>(sums[0], INT32_MAX);
     rep->last_delta = NAN;
     rep->max_violation = viol;
     rep->elapsed_ms = ms;
-    rep->kernel_ms = tacc.ms;
-    rep->kernel_launches = tacc.launches;
+    rep->kernel_ms = tacc ? tacc->ms : 0.0;
+    rep->kernel_launches = tacc ? tacc->launches : 0;
     rep->bytes_moved = 2.0 * sizeof(T) * (double)H * W * nph * (double)frames;
-    rep->window_projections = (double)cnt[1];
-    rep->pixel_updates = (double)cnt[2];
+    rep->window_projections = (double)sums[1];
+    rep->pixel_updates = (double)sums[2];
   }
-  return cnt[3] == 0 ? SMRE_OK : SMRE_NOT_CONVERGED;
+  return sums[3] == 0 ? SMRE_OK : SMRE_NOT_CONVERGED;
 }
 
 // ---------------------------------------------------------------- batches
@@ -1567,41 +1654,49 @@ void mc_tiles(const T* fields, int64_t fstride, int64_t ld, int H, int W, uint64
 }
 
 // Q (and optionally the per-side maxima) of fields f0 .. f0 + nf - 1, drawn
-// (GEN) or read from `fields`; results to host arrays.
+// (GEN) or read from `fields`; results to host arrays.  Device buffers: tmax
+// (min(nf, kMcChunk) * sd.n words) and q (min(nf, kMcChunk) doubles); acc may
+// be null (no per-kernel timing).
+template <bool GEN, typename T>
+int mc_run_buf(smre_ctx* c, const T* fields, int64_t ld, int64_t H, int64_t W, uint64_t seed,
+               int64_t f0, int64_t nf, const McSides& sd, double* q_out, double* tmax_out,
+               hipStream_t s, TimingAcc* acc, unsigned long long* tmax, double* q) {
+  int rc = SMRE_OK;
+  const int64_t fstride = H * ld;
+  for (int64_t done = 0; done < nf; done += kMcChunk) {
+    const int m = (int)std::min<int64_t>(kMcChunk, nf - done);
+    hipLaunchKernelGGL((fill_kernel<unsigned long long>), dim3(grid_for((int64_t)m * sd.n)),
+                       dim3(256), 0, s, tmax, (int64_t)m * sd.n, 0ull);
+    int slot = -1;
+    if (acc && (rc = timing_begin(c, *acc, s, &slot))) return rc;
+    const T* fp = GEN ? fields : fields + done * fstride;
+    if (sd.smax <= 8)
+      mc_tiles<GEN, T, 8>(fp, fstride, ld, (int)H, (int)W, seed, f0 + done, m, sd, tmax, s);
+    else if (sd.smax <= 16)
+      mc_tiles<GEN, T, 16>(fp, fstride, ld, (int)H, (int)W, seed, f0 + done, m, sd, tmax, s);
+    else
+      mc_tiles<GEN, T, 32>(fp, fstride, ld, (int)H, (int)W, seed, f0 + done, m, sd, tmax, s);
+    HIP_OK(hipGetLastError());
+    if (acc && (rc = timing_end(c, *acc, s, slot))) return rc;
+    hipLaunchKernelGGL(mc_q_kernel, dim3((m + 255) / 256), dim3(256), 0, s, tmax, m, sd, q);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(q_out + done, q, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+    if (tmax_out)
+      HIP_OK(hipMemcpyAsync(tmax_out + done * sd.n, tmax, sizeof(double) * (size_t)m * sd.n,
+                            hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));  // the buffers are reused by the next chunk
+  }
+  return acc ? timing_flush(c, *acc, true) : SMRE_OK;
+}
+
 template <bool GEN, typename T>
 int mc_run(smre_ctx* c, const T* fields, int64_t ld, int64_t H, int64_t W, uint64_t seed,
            int64_t f0, int64_t nf, const McSides& sd, double* q_out, double* tmax_out,
            hipStream_t s, TimingAcc& acc) {
   int rc = mc_buffers(c);
   if (rc) return rc;
-  const int64_t fstride = H * ld;
-  for (int64_t done = 0; done < nf; done += kMcChunk) {
-    const int m = (int)std::min<int64_t>(kMcChunk, nf - done);
-    hipLaunchKernelGGL((fill_kernel<unsigned long long>), dim3(grid_for((int64_t)m * sd.n)),
-                       dim3(256), 0, s, c->mc_tmax, (int64_t)m * sd.n, 0ull);
-    int slot;
-    rc = timing_begin(c, acc, s, &slot);
-    if (rc) return rc;
-    const T* fp = GEN ? fields : fields + done * fstride;
-    if (sd.smax <= 8)
-      mc_tiles<GEN, T, 8>(fp, fstride, ld, (int)H, (int)W, seed, f0 + done, m, sd, c->mc_tmax, s);
-    else if (sd.smax <= 16)
-      mc_tiles<GEN, T, 16>(fp, fstride, ld, (int)H, (int)W, seed, f0 + done, m, sd, c->mc_tmax, s);
-    else
-      mc_tiles<GEN, T, 32>(fp, fstride, ld, (int)H, (int)W, seed, f0 + done, m, sd, c->mc_tmax, s);
-    HIP_OK(hipGetLastError());
-    rc = timing_end(c, acc, s, slot);
-    if (rc) return rc;
-    hipLaunchKernelGGL(mc_q_kernel, dim3((m + 255) / 256), dim3(256), 0, s, c->mc_tmax, m, sd,
-                       c->mc_q);
-    HIP_OK(hipGetLastError());
-    HIP_OK(hipMemcpyAsync(q_out + done, c->mc_q, sizeof(double) * m, hipMemcpyDeviceToHost, s));
-    if (tmax_out)
-      HIP_OK(hipMemcpyAsync(tmax_out + done * sd.n, c->mc_tmax,
-                            sizeof(double) * (size_t)m * sd.n, hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));  // the buffers are reused by the next chunk
-  }
-  return timing_flush(c, acc, true);
+  return mc_run_buf<GEN, T>(c, fields, ld, H, W, seed, f0, nf, sd, q_out, tmax_out, s, &acc,
+                            c->mc_tmax, c->mc_q);
 }
 
 void mc_report(smre_report* rep, const TimingAcc& acc, float ms, int64_t H, int64_t W,
@@ -1747,7 +1842,11 @@ int admm_impl(smre_ctx* c, smre_dtype dt, const T* I_user, T* x_user, int64_t H,
       if (rc != SMRE_OK && rc != SMRE_NOT_CONVERGED) return rc;  // a capped block is fine here
       psweeps += pr.inner_sweeps;
     } else {
-      rc = smre_dykstra_project(c, dt, eps, H, W, W, p->full, nullptr, 0, s, &pr);
+      // every eps-step after the first may start from the previous one's
+      // increments (the input moves little between iterations)
+      smre_params fp = *p->full;
+      fp.warm = (p->warm && it > 1) ? 1 : 0;
+      rc = smre_dykstra_project(c, dt, eps, H, W, W, &fp, nullptr, 0, s, &pr);
       if (rc != SMRE_OK && rc != SMRE_NOT_CONVERGED) return rc;
       psweeps += pr.sweeps;
     }
@@ -1789,6 +1888,35 @@ int admm_impl(smre_ctx* c, smre_dtype dt, const T* I_user, T* x_user, int64_t H,
   return SMRE_OK;
 }
 
+}  // namespace
+
+namespace {
+int icd_validate(smre_ctx* c, smre_dtype dt, const void* x, int64_t H, int64_t W, int64_t ld,
+                 int64_t frames, int32_t K, const double* r2, int32_t n_phases,
+                 const int32_t* shift_y, const int32_t* shift_x, const int32_t* min_level,
+                 double tol, int32_t mode, int32_t max_inner) {
+  if (!c || !x || !r2 || !shift_y || !shift_x || !min_level) return SMRE_EINVAL;
+  if (frames < 1 || frames * H > INT32_MAX) return SMRE_EINVAL;
+  if (dt != SMRE_F32 && dt != SMRE_F64) return SMRE_EINVAL;
+  if (H < 1 || W < 1 || ld < W || H > (1 << 20) || W > (1 << 20)) return SMRE_EINVAL;
+  if (K < 0 || K > 5 || max_inner < 1 || n_phases < 1 || n_phases > 64) return SMRE_EINVAL;
+  {
+    // blocks of one frame: within the grid limits and below 2^31 per launch
+    const int64_t nbx = W / (1 << K) + 2, nby = H / (1 << K) + 2;
+    if (nby > 65535 || nbx * nby >= ((int64_t)1 << 31)) return SMRE_EINVAL;
+  }
+  for (int p = 0; p < n_phases; ++p)
+    if (shift_y[p] < 0 || shift_y[p] >= (1 << K) || shift_x[p] < 0 || shift_x[p] >= (1 << K) ||
+        min_level[p] < 0 || min_level[p] > K)
+      return SMRE_EINVAL;
+  if (mode != SMRE_TOL_MAXABS && mode != SMRE_TOL_MEANABS) return SMRE_EINVAL;
+  if (!std::isfinite(tol)) return SMRE_EINVAL;
+  for (int k = 0; k <= K; ++k) {
+    if (!std::isfinite(r2[k])) return SMRE_ENONFINITE;
+    if (!(r2[k] > 0)) return SMRE_EINVAL;
+  }
+  return SMRE_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -1947,27 +2075,10 @@ int smre_dykstra_incomplete_family(smre_ctx* c, smre_dtype dt, void* x, int64_t 
                                    const int32_t* shift_x, const int32_t* min_level, double tol,
                                    int32_t mode, int32_t max_inner, void* stream,
                                    smre_report* rep) {
-  if (!c || !x || !r2 || !shift_y || !shift_x || !min_level) return SMRE_EINVAL;
-  if (frames < 1 || frames * H > INT32_MAX) return SMRE_EINVAL;
-  if (dt != SMRE_F32 && dt != SMRE_F64) return SMRE_EINVAL;
-  if (H < 1 || W < 1 || ld < W || H > (1 << 20) || W > (1 << 20)) return SMRE_EINVAL;
-  if (K < 0 || K > 5 || max_inner < 1 || n_phases < 1 || n_phases > 64) return SMRE_EINVAL;
-  {
-    // blocks of one frame: within the grid limits and below 2^31 per launch
-    const int64_t nbx = W / (1 << K) + 2, nby = H / (1 << K) + 2;
-    if (nby > 65535 || nbx * nby >= ((int64_t)1 << 31)) return SMRE_EINVAL;
-  }
-  for (int p = 0; p < n_phases; ++p)
-    if (shift_y[p] < 0 || shift_y[p] >= (1 << K) || shift_x[p] < 0 || shift_x[p] >= (1 << K) ||
-        min_level[p] < 0 || min_level[p] > K)
-      return SMRE_EINVAL;
-  if (mode != SMRE_TOL_MAXABS && mode != SMRE_TOL_MEANABS) return SMRE_EINVAL;
-  if (!std::isfinite(tol)) return SMRE_EINVAL;
-  for (int k = 0; k <= K; ++k) {
-    if (!std::isfinite(r2[k])) return SMRE_ENONFINITE;
-    if (!(r2[k] > 0)) return SMRE_EINVAL;
-  }
-  int rc = set_device(c);
+  int rc = icd_validate(c, dt, x, H, W, ld, frames, K, r2, n_phases, shift_y, shift_x, min_level,
+                        tol, mode, max_inner);
+  if (rc) return rc;
+  rc = set_device(c);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   if (dt == SMRE_F64)
@@ -2133,7 +2244,8 @@ int smre_admm(smre_ctx* c, smre_dtype dt, const void* I, void* x, int64_t H, int
     for (int k = 0; k <= p->K; ++k)
       if (!(p->radius2_icd[k] > 0) || !std::isfinite(p->radius2_icd[k])) return SMRE_EINVAL;
   } else if (p->method == SMRE_ADMM_FULL) {
-    if (!p->full) return SMRE_EINVAL;
+    if (!p->full || p->full->warm != 0) return SMRE_EINVAL;
+    if (p->warm != 0 && p->warm != 1) return SMRE_EINVAL;
   } else {
     return SMRE_EINVAL;
   }
