@@ -169,6 +169,24 @@ int smre_dykstra_incomplete(smre_ctx* ctx, smre_dtype dtype, void* x, int64_t H,
                             int32_t tolmode, int32_t max_inner, int32_t num_phases, void* stream,
                             smre_report* report);
 
+/* smre_dykstra_incomplete for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): same arguments, same results and report (except kernel_ms and
+ * kernel_launches, which are 0: no per-kernel timing), but no hipMalloc,
+ * hipFree or other allocating call on any path.  Its device scratch (the work
+ * counters, their sums and the feasibility report's per-level maxima) is a
+ * fixed 32,960-byte static array per GPU, located when the context is created;
+ * it does not grow with the image, so the only size limit is K <= 5
+ * (SMRE_EINVAL beyond, as for smre_dykstra_incomplete).  Every call on one
+ * GPU uses that GPU's single copy and overwrites it: calls that overlap on one
+ * GPU (other host threads, other streams) race and must be serialised by the
+ * caller.  The context still holds the control block and events used by the
+ * input check and the report, allocated by smre_ctx_create. */
+int smre_dykstra_incomplete_noalloc(smre_ctx* ctx, smre_dtype dtype, void* x, int64_t H,
+                                    int64_t W, int64_t ld, int32_t K, const double* radius2,
+                                    double tol, int32_t tolmode, int32_t max_inner,
+                                    int32_t num_phases, void* stream, smre_report* report);
+
 /* The incomplete Dykstra on every frame of a movie (the paper preprocesses the
  * frames of a fluorescence time series with it, Sec. 4): frames of H x W (row
  * stride ld) stacked

@@ -122,6 +122,7 @@ def _load():
                                        ctypes.POINTER(Report)]
     L.smre_dykstra_incomplete.argtypes = [vp, ctypes.c_int, vp, i64, i64, i64, i32, dp, dbl,
                                           i32, i32, i32, vp, ctypes.POINTER(Report)]
+    L.smre_dykstra_incomplete_noalloc.argtypes = L.smre_dykstra_incomplete.argtypes
     L.smre_dykstra_incomplete_frames.argtypes = [vp, ctypes.c_int, vp, i64, i64, i64, i64, i32,
                                                  dp, dbl, i32, i32, i32, vp,
                                                  ctypes.POINTER(Report)]
@@ -162,7 +163,7 @@ _lib = _load()
 EXPORTS = ["smre_status_string", "smre_ctx_create", "smre_ctx_destroy", "smre_ctx_set_timing",
            "smre_chi2_bounds", "smre_paper_bounds", "smre_workspace_size",
            "smre_dykstra_project", "smre_dykstra_incomplete", "smre_dykstra_incomplete_frames",
-           "smre_dykstra_incomplete_family",
+           "smre_dykstra_incomplete_family", "smre_dykstra_incomplete_noalloc",
            "smre_max_violation",
            "smre_batch_workspace_size", "smre_dykstra_project_batch", "smre_serve_create",
            "smre_serve_destroy", "smre_serve_submit", "smre_serve_poll", "smre_serve_stats",
@@ -323,6 +324,26 @@ class Context:
                                           int(max_inner), int(num_phases), _stream(stream),
                                           ctypes.byref(rep))
         _check(rc, "smre_dykstra_incomplete", allow=(OK, NOT_CONVERGED))
+        return rep.as_dict()
+
+    def incomplete_noalloc(self, x, K, radius2, tol=1e-3, mode=TOL_MEANABS, max_inner=10000,
+                           num_phases=None, stream=None):
+        """As incomplete(), through the entry point that allocates no device
+        memory (its scratch is a fixed static array per GPU; overlapping calls
+        on one GPU race)."""
+        H, W, ld = _image(x)
+        r, rp = _dvec(radius2)
+        if len(r) != K + 1:
+            raise ValueError("radius2 needs K+1 entries")
+        if num_phases is None:
+            num_phases = K + 1
+        rep = Report()
+        rc = _lib.smre_dykstra_incomplete_noalloc(self._h, _dtype_code(x),
+                                                  ctypes.c_void_p(x.data_ptr()), H, W, ld, int(K),
+                                                  rp, float(tol), int(mode), int(max_inner),
+                                                  int(num_phases), _stream(stream),
+                                                  ctypes.byref(rep))
+        _check(rc, "smre_dykstra_incomplete_noalloc", allow=(OK, NOT_CONVERGED))
         return rep.as_dict()
 
     def incomplete_frames(self, x, K, radius2, tol=1e-3, mode=TOL_MEANABS, max_inner=10000,

@@ -602,6 +602,37 @@ constexpr int64_t kIcdCntWords = (int64_t)kIcdSlots * kIcdSlotWords;
 // rounded up), the statistic
 constexpr int64_t kIcdScratchWords = kIcdCntWords + 8 + 8 + 8;
 
+}  // namespace
+
+// Device scratch of smre_dykstra_incomplete_noalloc (32,960 bytes, held by every
+// GPU the library runs on until the process ends).  In host code `scratch`
+// names a host-side stand-in: kernels get its device address, looked up per
+// device with hipGetSymbolAddress when a context is created.
+static __device__ __align__(256) unsigned long long scratch[kIcdScratchWords];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned long long* g_scratch_ptr[kMaxDevices] = {};
+
+// With `device` current: record the device address of `scratch` on it.
+int scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return SMRE_EINVAL;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return SMRE_OK;
+  void* p = nullptr;
+  HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) return SMRE_EDEVICE;
+  g_scratch_ptr[device] = (unsigned long long*)p;
+  return SMRE_OK;
+}
+
+unsigned long long* scratch_of(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
 
 // Phase p: lattice shift (sy[p], sx[p]), levels K down to lo[p].  fixed:
 // caller-supplied device scratch (one frame; no allocation on any path, no
@@ -1947,6 +1978,7 @@ int smre_ctx_create(int device, smre_ctx** out) {
   c->device = device;
   int rc = set_device(c);
   if (!rc) rc = ensure_ctrl(c);
+  if (!rc) rc = scratch_init(device);
   if (rc) {
     smre_ctx_destroy(c);
     return rc;
@@ -2086,6 +2118,35 @@ int smre_dykstra_incomplete_family(smre_ctx* c, smre_dtype dt, void* x, int64_t 
                             shift_y, shift_x, min_level, s, rep);
   return icd_impl<float>(c, x, H, W, ld, frames, K, r2, tol, mode, max_inner, n_phases, shift_y,
                          shift_x, min_level, s, rep);
+}
+
+int smre_dykstra_incomplete_noalloc(smre_ctx* c, smre_dtype dt, void* x, int64_t H, int64_t W,
+                                    int64_t ld, int32_t K, const double* r2, double tol,
+                                    int32_t mode, int32_t max_inner, int32_t nph, void* stream,
+                                    smre_report* rep) {
+  if (K < 0 || K > 5 || nph < 1 || nph > K + 1) return SMRE_EINVAL;
+  int32_t sy[6], sx[6], lo[6];
+  for (int i = 0; i < nph; ++i) {
+    sy[i] = sx[i] = (1 << i) & ((1 << K) - 1);
+    lo[i] = i;
+  }
+  int rc = icd_validate(c, dt, x, H, W, ld, 1, K, r2, nph, sy, sx, lo, tol, mode, max_inner);
+  if (rc) return rc;
+  // the scratch holds the counters, their sums, one maximum per level (at
+  // most 8) and one statistic, whatever the image size
+  if (K + 1 > 8) return SMRE_ETOOBIG;
+  rc = set_device(c);
+  if (rc) return rc;
+  unsigned long long* base = scratch_of(c->device);
+  if (!base) return SMRE_EDEVICE;  // set up when the context was created
+  const IcdScratch fs{base, base + kIcdCntWords, base + kIcdCntWords + 8,
+                      (double*)(base + kIcdCntWords + 16)};
+  hipStream_t s = (hipStream_t)stream;
+  if (dt == SMRE_F64)
+    return icd_impl<double>(c, x, H, W, ld, 1, K, r2, tol, mode, max_inner, nph, sy, sx, lo, s,
+                            rep, true, &fs);
+  return icd_impl<float>(c, x, H, W, ld, 1, K, r2, tol, mode, max_inner, nph, sy, sx, lo, s, rep,
+                         true, &fs);
 }
 
 int smre_batch_workspace_size(smre_dtype dt, int32_t n, const smre_batch_image* im,
