@@ -490,10 +490,10 @@ def cpu_baseline_sofi(movie, K, r2, budget_s=12.0):
             "sample": f"first {n} frames of the movie ({H}x{W}), {el:.1f} s"}
 
 
-def frc_summary(a, b):
-    """Fourier ring correlation of two images: per ring of integer radius r,
-    Re sum A conj(B) / sqrt(sum |A|^2 sum |B|^2) over the ring; returned as
-    the mean over rings up to Nyquist and the first ring below 1/7."""
+def frc_rings(a, b):
+    """Fourier ring correlation of two images: for each ring of integer radius
+    r = 1 .. min(H, W) / 2 about the centred spectrum, Re sum A conj(B) /
+    sqrt(sum |A|^2 sum |B|^2) over the ring (0 for a ring without energy)."""
     A = np.fft.fftshift(np.fft.fft2(a))
     B = np.fft.fftshift(np.fft.fft2(b))
     H, W = a.shape
@@ -503,7 +503,14 @@ def frc_summary(a, b):
     num = np.bincount(ring, (A * np.conj(B)).real.ravel(), minlength=nr + 1)[1:nr + 1]
     da = np.bincount(ring, (np.abs(A) ** 2).ravel(), minlength=nr + 1)[1:nr + 1]
     db = np.bincount(ring, (np.abs(B) ** 2).ravel(), minlength=nr + 1)[1:nr + 1]
-    frc = num / np.sqrt(np.maximum(da * db, 1e-300))
+    return num / np.sqrt(np.maximum(da * db, 1e-300))
+
+
+def frc_summary(a, b):
+    """frc_rings summarised: the mean over rings up to Nyquist, the minimum and
+    the first ring below 1/7."""
+    frc = frc_rings(a, b)
+    nr = len(frc)
     below = np.nonzero(frc < 1.0 / 7.0)[0]
     return {"mean": float(frc.mean()), "min": float(frc.min()),
             "first_ring_below_1_7": int(below[0]) + 1 if below.size else None, "rings": nr}
