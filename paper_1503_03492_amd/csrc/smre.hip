@@ -694,8 +694,20 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t fra
     // frames per launch: at most 65535 and fewer than 2^31 blocks in all
     const int64_t fchunk = std::max<int64_t>(
         1, std::min<int64_t>(65535, ((int64_t)1 << 31) / ((int64_t)nbx * nby) - 1));
+    a.nx_d = (uint32_t)nbx;
+    a.nxy_d = (uint32_t)nbx * (uint32_t)nby;
+    udiv_magic(a.nx_d, &a.nx_m, &a.nx_s);
+    udiv_magic(a.nxy_d, &a.nxy_m, &a.nxy_s);
     for (int64_t f0 = 0; f0 < frames; f0 += fchunk) {
-      const dim3 grid(nbx, nby, (unsigned)std::min<int64_t>(fchunk, frames - f0));
+      const int64_t nf = std::min<int64_t>(fchunk, frames - f0);
+      a.nblocks = (uint32_t)(nf * nbx * nby);
+      // runs of blocks per wave once there are enough blocks to keep every
+      // SIMD busy with several waves (wave launches are then the cost to
+      // amortise); one block per wave below that
+      const int64_t simds = (int64_t)std::max(1, c->cus) * 4;
+      a.run = a.nblocks >= (uint32_t)(simds * 8 * 16) ? 16u
+              : a.nblocks >= (uint32_t)(simds * 8 * 4) ? 4u : 1u;
+      const dim3 grid((a.nblocks + a.run - 1) / a.run);
       a.x = (T*)x + f0 * H * ld;
       if (mode == SMRE_TOL_MEANABS)
         launch_icd<T, true>(K, grid, a, s);
