@@ -295,20 +295,34 @@ def test_config2_two_sweeps_match_oracle(ctx):
     assert relerr(z64, ref) <= 1e-12
 
 
-def test_config3_properties(ctx):
-    """1024^2, 2000 emitters, sides 1..16, FP32 to tol 1e-5: properties that hold
-    at any size -- feasibility, |z| <= |x0|, z x0 >= 0, oddness."""
+def test_config3_against_stored_oracle(ctx):
+    """1024^2, 2000 emitters, sides 1..16, FP32 to tol 1e-5, the launch
+    configuration of the benchmark, against the FP64 oracle's projection of
+    the same float32 input in the same order (R = 16) and with the same
+    stopping rule, stored by tests/golden/make_dykstra_1024sq.py (oracle/
+    only): same stopping sweep, max-abs error within 1e-5 of max|z|, the same
+    feasibility figure; and the properties that hold at any size."""
+    import hashlib
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "dykstra_1024sq_sides1-16_r16.npz")
+    g = np.load(path, allow_pickle=False)
     x0 = gi.emitters(1024, 1024, n_e=2000, seed=0).astype(np.float32)
+    assert hashlib.sha256(x0.tobytes()).hexdigest() == str(g["input_sha256"])
     sides = list(range(1, 17))
     r2 = oracle.chi2_bounds(sides)
+    np.testing.assert_array_equal(r2, g["radius2"])
     x = dev(x0, torch.float32)
-    rc, rep = ctx.project(x, sides, r2, tol=1e-5, max_sweeps=4000)
+    rc, rep = ctx.project(x, sides, r2, tol=1e-5, max_sweeps=4000, region=16)
     assert rep["converged"] == 1
     z = x.double().cpu().numpy()
-    # Stopping at max change < 1e-5 while the sweep map contracts slowly
-    # (~2400 sweeps to tol) leaves the iterate O(tol / (1 - rate)) from the
-    # limit: a few 1e-4 in sum z^2 / r2.
-    assert rep["max_violation"] <= 1e-3
+    ref = g["z_tol1e-05"]
+    err = relerr(z, ref)
+    print(f"1024^2 FP32 vs oracle at the same rule: {err:.3e}; sweeps {rep['sweeps']} vs "
+          f"{int(g['sweeps_tol1e-05'])}; violation {rep['max_violation']:.4e} vs "
+          f"{float(g['violation_tol1e-05']):.4e}")
+    assert rep["sweeps"] == int(g["sweeps_tol1e-05"])
+    assert err <= 1e-5
+    assert rep["max_violation"] == pytest.approx(float(g["violation_tol1e-05"]), rel=1e-2)
     assert np.all(np.abs(z) <= np.abs(x0) + 1e-6)
     assert np.all(z * x0 >= -1e-12)
 
