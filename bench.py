@@ -676,6 +676,8 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--max-active", type=int, default=16)
     ap.add_argument("--serve-baseline", action="store_true")
+    ap.add_argument("--no-kahan", action="store_true",
+                    help="plain FP32 window sums instead of the compensated ones")
     ap.add_argument("--guard", type=float, default=1e-5,
                     help="relative band around the bound in which FP32 window sums are "
                          "rechecked in FP64")
@@ -718,7 +720,7 @@ def main():
     ctx = smre.Context(0)
     ctx.set_timing(True)
     opts = smre.ProjectOptions(tol=wl["tol"], max_sweeps=wl["max_sweeps"], check_every=1,
-                               region=args.region, kahan=True, guard_rel=args.guard,
+                               region=args.region, kahan=not args.no_kahan, guard_rel=args.guard,
                                inc=smre.INC_BF16 if wl["inc"] == "bf16" else smre.INC_SAME)
 
     def step():
@@ -736,7 +738,8 @@ def main():
         del a, b
         x.copy_(x0_dev)
         prof = smre.ProjectOptions(tol=0.0, max_sweeps=args.profile_sweeps, check_every=1,
-                                   region=args.region, kahan=True, guard_rel=args.guard,
+                                   region=args.region, kahan=not args.no_kahan,
+                                   guard_rel=args.guard,
                                    inc=opts.inc)
         rc, rep = ctx.project(x, sides, r2, prof)
         torch.cuda.synchronize()
@@ -784,7 +787,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["workload"], "H": H, "W": W, "sides": f"1..{sides[-1]}",
                    "tol": wl["tol"], "increments": wl["inc"], "region": reps[0]["region"],
-                   "guard_rel": args.guard},
+                   "guard_rel": args.guard, "kahan": not args.no_kahan},
         "time_to_tol_ms": el / args.steps * 1e3,
         "sweeps_to_tol": sweeps,
         "converged": all(r["converged"] for r in reps),

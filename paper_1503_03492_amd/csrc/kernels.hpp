@@ -459,7 +459,10 @@ __device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs
       }
     // 2) y = x + I (pixels outside the window count as 0), sum of squares
     TX y[U][V];
-    TX acc = 0, comp = 0;
+    // FP32: two interleaved accumulators (even / odd elements), each with its
+    // own compensation when KAHAN, so the dependent add chains are half as
+    // long; the corrected partial sums are added at the end.
+    TX acc[2] = {0, 0}, comp[2] = {0, 0};
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -471,19 +474,23 @@ __device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs
         else if (part_r) yv = rl ? yv : TX(0);
         else if (part_c) yv = cl ? yv : TX(0);
         y[u][v] = yv;
+        const int h = (sizeof(TX) == 4) ? ((u * V + v) & 1) : 0;
         if constexpr (sizeof(TX) == 4 && KAHAN) {
-          const TX t2 = __builtin_fmaf(yv, yv, -comp);
-          const TX s2 = acc + t2;
-          comp = (s2 - acc) - t2;
-          acc = s2;
+          const TX t2 = __builtin_fmaf(yv, yv, -comp[h]);
+          const TX s2 = acc[h] + t2;
+          comp[h] = (s2 - acc[h]) - t2;
+          acc[h] = s2;
         } else if constexpr (sizeof(TX) == 4) {
-          acc = __builtin_fmaf(yv, yv, acc);
+          acc[h] = __builtin_fmaf(yv, yv, acc[h]);
         } else {
-          acc = __builtin_fma(yv, yv, acc);
+          acc[0] = __builtin_fma(yv, yv, acc[0]);
         }
       }
-    if constexpr (sizeof(TX) == 4 && KAHAN) acc -= comp;
-    const TX n = group_sum<G>(acc);
+    TX lane_sum;
+    if constexpr (sizeof(TX) == 4 && KAHAN) lane_sum = (acc[0] - comp[0]) + (acc[1] - comp[1]);
+    else if constexpr (sizeof(TX) == 4) lane_sum = acc[0] + acc[1];
+    else lane_sum = acc[0];
+    const TX n = group_sum<G>(lane_sum);
 
     // 3) x' = t y into the footprint, I' = y - x' into the ring (pixels
     //    first, then increments, so neighbouring writes merge)
@@ -537,6 +544,10 @@ __device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs
     } else {
       write_step(n > r2 ? __builtin_sqrt(r2 / n) : TX(1));
     }
+    // (the copy below reads, as 16-byte words, increments this lane and
+    // others have just stored as elements: keep the compiler from hoisting it
+    // above those stores, which alias analysis would allow for another type)
+    __asm__ volatile("" ::: "memory");
     // a round that ran into the mirrored pages copies them back
     if (__builtin_expect(roff + nbytes > (uint32_t)(kSlots * kPage), 0)) {
       const int np = (int)((roff + nbytes - kSlots * kPage + kPage - 1) / kPage);
