@@ -227,13 +227,17 @@ def bench_serve(args):
 
     import paper_1503_03492_amd as smre
     import smre_inputs as gi
-    times, sides_px, kids = gi.serve_trace(args.serve_n, rate=args.rate, seed=0)
+    nw = args.serve_warmup
+    times, sides_px, kids = gi.serve_trace(args.serve_n + nw, rate=args.rate, seed=0)
     imgs = [gi.serve_image(s, k).astype(np.float32) for s, k in zip(sides_px, kids)]
     wsides = [gi.serve_sides(s) for s in sides_px]
     bounds = [smre.chi2_bounds(w) for w in wsides]
     srv = smre.Server(max_active=args.max_active, queue_cap=100000)
     lat = [None] * len(imgs)
     done_at = [None] * len(imgs)
+    outs = [None] * len(imgs)
+    # served results checked afterwards: the three smallest measured requests
+    sample = set(sorted(range(nw, len(imgs)), key=lambda i: sides_px[i])[:3])
     tickets = [None] * len(imgs)
     t_start = time.perf_counter()
 
@@ -255,16 +259,50 @@ def bench_serve(args):
             if r is not None:
                 lat[i] = r[3]
                 done_at[i] = time.perf_counter() - t_start
+                outs[i] = (r[1], r[2]) if i in sample else None
                 pending.discard(i)
                 if len(pending) % 10 == 0:
                     print(f"served {len(imgs) - len(pending)}", file=sys.stderr, flush=True)
         time.sleep(0.001)
     th.join()
-    span = max(done_at)
+    st = srv.stats()
     srv.close()
-    res = {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-           "throughput_req_s": len(imgs) / span, "requests": len(imgs),
-           "offered_rate_req_s": args.rate}
+    # measured requests: after the warm-up ones; throughput over their span
+    mlat = lat[nw:]
+    t_first = times[nw]
+    span = max(done_at[nw:]) - t_first
+    res = {"p50_s": float(np.percentile(mlat, 50)), "p99_s": float(np.percentile(mlat, 99)),
+           "throughput_req_s": len(mlat) / span, "requests": len(mlat),
+           "warmup_requests": nw, "offered_rate_req_s": args.rate,
+           "peak_active": st["peak_active"], "joined_running": st["joined_running"]}
+    # each sampled served result against the same image solved alone (FP32,
+    # R = 16: the arithmetic the server runs) and against the FP64 oracle at the
+    # same order and stopping rule
+    checks = []
+    ctx1 = smre.Context(0)
+    for i in sorted(sample):
+        z, rep = outs[i]
+        x = torch.from_numpy(imgs[i]).cuda()
+        _, rep1 = ctx1.project(x, wsides[i], bounds[i], tol=1e-5, max_sweeps=6000, region=16)
+        torch.cuda.synchronize()
+        alone = x.cpu().numpy()
+        chk = {"side": int(sides_px[i]), "sweeps": rep["sweeps"],
+               "alone_sweeps": rep1["sweeps"], "bitwise_equal_alone": bool(np.array_equal(z, alone))}
+        if args.serve_oracle_check and len(checks) == 0:
+            import oracle
+            oracle.set_threads(host_cores())
+            try:
+                ref, osw, _ = oracle.dykstra(imgs[i].astype(np.float64), wsides[i], bounds[i],
+                                             tol=1e-5, max_sweeps=6000,
+                                             order=oracle.ORDER_REGION, region=16)
+            finally:
+                oracle.set_threads(1)
+            chk["err_vs_oracle"] = float(np.max(np.abs(z - ref)) / np.max(np.abs(ref)))
+            chk["oracle_sweeps"] = osw
+        checks.append(chk)
+        print(f"checked served request {i}: {chk}", file=sys.stderr, flush=True)
+    ctx1.close()
+    res["sample_checks"] = checks
     # baseline: the same trace, one FP64 solve at a time
     base_lat = []
     if args.serve_baseline:
@@ -279,15 +317,16 @@ def bench_serve(args):
             clock = start + (time.perf_counter() - t0)
             base_lat.append(clock - times[i])
             print(f"baseline {i + 1}/{len(imgs)}", file=sys.stderr, flush=True)
-        res["baseline_fp64_fifo"] = {"p50_s": float(np.percentile(base_lat, 50)),
-                                     "p99_s": float(np.percentile(base_lat, 99)),
+        res["baseline_fp64_fifo"] = {"p50_s": float(np.percentile(base_lat[nw:], 50)),
+                                     "p99_s": float(np.percentile(base_lat[nw:], 99)),
                                      "throughput_req_s": len(imgs) / clock}
     out = {"metric": "p50/p99 serve latency and throughput (continuous batching)",
            "value": res["throughput_req_s"], "unit": "requests/s", "n_gpus": 1, "steps": 1,
-           "warmup": 0, "ms_per_step": span * 1e3, "higher_is_better": True, "scaling": "weak",
+           "warmup": nw, "ms_per_step": span * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "serve_poisson_256-1024_sides1-max(8,side/64)_tol1e-5",
-                      "max_active": args.max_active}, "serve": res}
+                      "max_active": args.max_active}, "serve": res,
+           "roofline": None}
     print(json.dumps(out), flush=True)
 
 
@@ -685,6 +724,11 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--max-active", type=int, default=16)
     ap.add_argument("--serve-baseline", action="store_true")
+    ap.add_argument("--serve-warmup", type=int, default=20,
+                    help="serve workload: requests at the head of the trace left out of "
+                         "the latency figures")
+    ap.add_argument("--serve-oracle-check", type=int, default=1,
+                    help="serve workload: compare the smallest sampled result with the oracle")
     ap.add_argument("--no-kahan", action="store_true",
                     help="plain FP32 window sums instead of the compensated ones")
     ap.add_argument("--guard", type=float, default=1e-5,

@@ -288,6 +288,8 @@ typedef struct {
 
 typedef struct {
   int64_t submitted, completed, rejected, failed, active, queued, sweeps, bytes_in_use;
+  int64_t peak_active;     /* most requests on the device at once */
+  int64_t joined_running;  /* admissions while other requests were mid-solve */
 } smre_serve_counters;
 
 int smre_serve_create(const smre_serve_config* cfg, smre_server** out);

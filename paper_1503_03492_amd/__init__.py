@@ -72,7 +72,8 @@ class ServeConfig(ctypes.Structure):
 
 class ServeCounters(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "rejected", "failed",
-                                              "active", "queued", "sweeps", "bytes_in_use")]
+                                              "active", "queued", "sweeps", "bytes_in_use",
+                                              "peak_active", "joined_running")]
 
 
 class AdmmParams(ctypes.Structure):

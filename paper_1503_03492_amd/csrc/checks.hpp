@@ -83,6 +83,10 @@ __global__ void decide_kernel(Ctrl* ctrl, double tol, int sweep) {
   }
 }
 
+// Clears the non-finite flag before a check (the flag is only ever raised
+// by the check itself).
+__global__ void nonfinite_reset_kernel(Ctrl* ctrl) { ctrl->nonfinite = 0; }
+
 template <typename TX>
 __global__ __launch_bounds__(256) void nonfinite_kernel(const TX* x, int64_t ld, int H, int W,
                                                         Ctrl* ctrl) {

@@ -76,6 +76,8 @@ struct Stats {
   int64_t submitted = 0, completed = 0, rejected = 0, failed = 0;
   int64_t active = 0, queued = 0, sweeps = 0;
   size_t bytes_in_use = 0;
+  int64_t peak_active = 0;     // most requests on the device at once
+  int64_t joined_running = 0;  // admissions while other requests were mid-solve
 };
 
 class Server {
@@ -219,8 +221,10 @@ class Server {
           r->t_admit = now_s();
           slot_req_[s] = r;
           used_ += r->footprint;
+          if (active_ > 0) stats_.joined_running++;
           ++active_;
           stats_.active = active_;
+          if (active_ > stats_.peak_active) stats_.peak_active = active_;
         }
         if (active_ == 0 || failed_) continue;
       }

@@ -330,6 +330,9 @@ void problem_signature(smre_dtype dt, int64_t H, int64_t W, const smre_params* p
 int ensure_ctrl(smre_ctx* c) {
   if (!c->ctrl) {
     HIP_OK(hipMalloc(&c->ctrl, sizeof(Ctrl)));
+    hipLaunchKernelGGL(ctrl_reset_kernel, dim3(1), dim3(1), 0, 0, c->ctrl);  // defined contents
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(0));
     HIP_OK(hipHostMalloc(&c->ctrl_host, sizeof(Ctrl) * (kLag + 2), hipHostMallocDefault));
     HIP_OK(hipMalloc(&c->counter, 64));
     c->lag_ev.resize(kLag + 2);
@@ -411,6 +414,8 @@ int run_violation(smre_ctx* c, const void* x, int64_t H, int64_t W, int64_t ld, 
 template <typename TX>
 int check_nonfinite(smre_ctx* c, const void* x, int64_t H, int64_t W, int64_t ld, hipStream_t s,
                     bool* bad) {
+  // every caller gets a cleared flag, whatever the control block held before
+  hipLaunchKernelGGL(nonfinite_reset_kernel, dim3(1), dim3(1), 0, s, c->ctrl);
   hipLaunchKernelGGL((nonfinite_kernel<TX>), dim3(grid_rows(H)), dim3(256), 0, s,
                      (const TX*)x, ld, (int)H, (int)W, c->ctrl);
   HIP_OK(hipGetLastError());
@@ -2377,6 +2382,8 @@ int smre_serve_stats(smre_server* s, smre_serve_counters* out) {
   out->queued = st.queued;
   out->sweeps = st.sweeps;
   out->bytes_in_use = (int64_t)st.bytes_in_use;
+  out->peak_active = st.peak_active;
+  out->joined_running = st.joined_running;
   return SMRE_OK;
 }
 

@@ -138,6 +138,10 @@ int main(int argc, char** argv) {
     }
     CHECK(f->max_active <= 4);
     CHECK(s.stats().completed == 10);
+    // the scheduler's own count of co-resident requests agrees with the
+    // backend's, and requests joined a running mix
+    CHECK(s.stats().peak_active == f->max_active && f->max_active >= 2);
+    CHECK(s.stats().joined_running >= 1);
     std::printf("ok basic\n");
   }
   if (only.empty() || only == "admission") {
@@ -154,6 +158,7 @@ int main(int argc, char** argv) {
       CHECK(wait(s, tk, out, nullptr) == SMRE_OK);
     }
     CHECK(f->max_active == 1);
+    CHECK(s.stats().peak_active == 1 && s.stats().joined_running == 0);
     std::vector<float> big(400, 1.0f);
     uint64_t tk;
     const smre_params p = params(1e-2, 10, sides, r2, 1);

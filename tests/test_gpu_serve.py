@@ -50,14 +50,21 @@ def test_alone_and_in_mix_identical(smre):
         reqs.append((x0, sides, oracle.chi2_bounds(sides), [1e-4, 1e-5][k % 2]))
     srv = smre.Server(max_active=3, queue_cap=64)
     # staggered arrivals: later requests join while earlier ones are running
-    tickets = []
-    for x0, sides, r2, tol in reqs:
+    tickets = [srv.submit(*reqs[0][:3], tol=reqs[0][3], max_sweeps=4000)]
+    t0 = time.time()
+    while srv.stats()["active"] < 1 and time.time() - t0 < 30:
+        time.sleep(0.001)
+    for x0, sides, r2, tol in reqs[1:]:
         tickets.append(srv.submit(x0, sides, r2, tol=tol, max_sweeps=4000))
         time.sleep(0.003)
     outs = [wait(srv, t, r[0].shape) for t, r in zip(tickets, reqs)]
     st = srv.stats()
     srv.close()
     assert st["completed"] == len(reqs)
+    # the mix really shared the device: several requests at once, and requests
+    # admitted while others were part-way through their sweeps
+    print(f"peak active {st['peak_active']}, joined a running mix {st['joined_running']}")
+    assert st["peak_active"] >= 2 and st["joined_running"] >= 1
     for (x0, sides, r2, tol), (rc, z, rep, lat) in zip(reqs, outs):
         ref, rep1 = single(smre, x0, sides, r2, tol, 4000)
         assert rc == 0 and rep["converged"] == 1
