@@ -54,6 +54,8 @@ typedef enum {
 typedef enum { SMRE_F32 = 0, SMRE_F64 = 1 } smre_dtype;       /* dtype of x        */
 typedef enum { SMRE_INC_SAME = 0, SMRE_INC_BF16 = 1 } smre_inc; /* increment storage */
 typedef enum { SMRE_TOL_MAXABS = 0, SMRE_TOL_MEANABS = 1 } smre_tolmode;
+/* Cyclic order of the full projection (see "Sweep order" below). */
+typedef enum { SMRE_ORDER_REGION = 0, SMRE_ORDER_DESC = 1, SMRE_ORDER_ASC = 2 } smre_order;
 
 typedef struct smre_ctx smre_ctx;
 
@@ -85,13 +87,19 @@ typedef struct smre_ctx smre_ctx;
  *                     re-summed in FP64 before the threshold test (0 = off)
  *
  * Sweep order.  Dykstra's limit does not depend on the cyclic order of the
- * sets (Sec. 2.3), so the library uses an order that needs no ordering
- * between overlapping sets inside a kernel: the anchor (top-left) plane is cut
- * into R x R regions coloured 2 (p mod 2) + (q mod 2); colour by colour, each
- * region (p, q) visits its windows side by side (descending), then offset
- * (a', b') in raster order, where offset (a', b') selects the windows anchored
- * at (p R + a' + s i, q R + b' + s j) -- disjoint, so projected together.
- * Regions of one colour touch disjoint pixels.
+ * sets (Sec. 2.3).  order = SMRE_ORDER_REGION (the default, and the fast one)
+ * needs no ordering between overlapping sets inside a kernel: the anchor
+ * (top-left) plane is cut into R x R regions coloured 2 (p mod 2) + (q mod 2);
+ * colour by colour, each region (p, q) visits its windows side by side
+ * (descending), then offset (a', b') in raster order, where offset (a', b')
+ * selects the windows anchored at (p R + a' + s i, q R + b' + s j) --
+ * disjoint, so projected together.  Regions of one colour touch disjoint
+ * pixels.  SMRE_ORDER_DESC / SMRE_ORDER_ASC: the canonical orders -- sides
+ * descending / ascending, for each side s its s^2 tilings (a, b) in raster
+ * order, a tiling being the disjoint windows anchored at (a + s i, b + s j);
+ * one launch per tiling (several times slower: every launch re-reads the
+ * image), the iterates of the paper's own visiting order (Algorithm 2 with
+ * the sets grouped by tiling).  region is ignored for those orders.
  */
 typedef struct {
   int32_t n_sides;
@@ -105,6 +113,8 @@ typedef struct {
   int32_t kahan;
   int32_t warm;
   double guard_rel;
+  int32_t order;      /* smre_order */
+  int32_t reserved1;  /* 0 */
 } smre_params;
 
 typedef struct {

@@ -19,6 +19,7 @@ NOT_CONVERGED = 1
 PENDING = 2
 F32, F64 = 0, 1
 INC_SAME, INC_BF16 = 0, 1
+ORDER_REGION, ORDER_DESC, ORDER_ASC = 0, 1, 2
 TOL_MAXABS, TOL_MEANABS = 0, 1
 
 
@@ -33,7 +34,8 @@ class Params(ctypes.Structure):
                 ("radius2", ctypes.POINTER(ctypes.c_double)), ("tol", ctypes.c_double),
                 ("max_sweeps", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("region", ctypes.c_int32), ("inc", ctypes.c_int32), ("kahan", ctypes.c_int32),
-                ("warm", ctypes.c_int32), ("guard_rel", ctypes.c_double)]
+                ("warm", ctypes.c_int32), ("guard_rel", ctypes.c_double),
+                ("order", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -248,6 +250,8 @@ class ProjectOptions:
     # start from the increments the previous call on the same problem left in
     # the workspace (the context's cached one, or the one passed)
     warm: bool = False
+    # cyclic order: ORDER_REGION (default) or the canonical ORDER_DESC / ORDER_ASC
+    order: int = ORDER_REGION
 
 
 class Context:
@@ -281,7 +285,7 @@ class Context:
             raise ValueError("sides and radius2 differ in length")
         p = Params(len(s), sp, rp, float(o.tol), int(o.max_sweeps), int(o.check_every),
                    int(o.region), int(o.inc), 1 if o.kahan else 0, 1 if o.warm else 0,
-                   float(o.guard_rel))
+                   float(o.guard_rel), int(o.order), 0)
         return p, (s, r)
 
     def workspace_size(self, dtype, H, W, sides, radius2, opts=None):

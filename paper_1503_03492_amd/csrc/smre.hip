@@ -27,6 +27,7 @@
 #include "checks.hpp"
 #include "kernels.hpp"
 #include "mc.hpp"
+#include "canon.hpp"
 #include "admm.hpp"
 #include "serve_core.hpp"
 #include "smre.h"
@@ -217,6 +218,7 @@ int plan_project(smre_dtype dt, int64_t H, int64_t W, const smre_params* p, Plan
   if (p->inc != SMRE_INC_SAME && p->inc != SMRE_INC_BF16) return SMRE_EINVAL;
   if (p->inc == SMRE_INC_BF16 && dt != SMRE_F32) return SMRE_EINVAL;
   if (p->warm != 0 && p->warm != 1) return SMRE_EINVAL;
+  if (p->order < SMRE_ORDER_REGION || p->order > SMRE_ORDER_ASC) return SMRE_EINVAL;
   if (!std::isfinite(p->tol) || !std::isfinite(p->guard_rel) || p->guard_rel < 0)
     return SMRE_EINVAL;
   std::vector<std::pair<int, double>> sd;
@@ -563,6 +565,190 @@ int project_impl(smre_ctx* c, smre_dtype dt, void* x, int64_t H, int64_t W, int6
     rep->elapsed_ms = ms;
     rep->kernel_ms = tacc.ms;
     rep->kernel_launches = tacc.launches;
+    rep->bytes_moved = (double)sweeps_run * (2.0 * es * (double)pl.nq + 2.0 * sizeof(TX) * (double)H * W);
+    rep->window_projections = (double)sweeps_run * (double)pl.nwin;
+    rep->pixel_updates = (double)sweeps_run * (double)pl.nq;
+  }
+  if (checking && !fin.done) return SMRE_NOT_CONVERGED;
+  return SMRE_OK;
+}
+
+
+// ---------------------------------------------------------------- canonical orders
+// Full Dykstra with the sides descending (or ascending) and each side's
+// tilings (a, b) in raster order, one launch per tiling (canon.hpp).
+struct CanonTiling {
+  int s, a, b, nr, nc, k;  // side, offset, window rows / columns, side index
+  size_t off;              // first byte of the tiling's increment plane
+};
+struct CanonPlan {
+  std::vector<CanonTiling> t;
+  Plan base;  // sorted sides, bounds, counts (the region fields are unused)
+  size_t qbytes = 0, off_prev = 0, off_isum = 0, off_sig = 0, total = 0;
+};
+
+int plan_canon(smre_dtype dt, int64_t H, int64_t W, const smre_params* p, CanonPlan* cp) {
+  // the region planner validates the sides, bounds and options (the region
+  // side plays no part in these orders)
+  smre_params q = *p;
+  q.region = 0;
+  int rc = plan_project(dt, H, W, &q, &cp->base, false);
+  if (rc) return rc;
+  const Plan& pl = cp->base;
+  const size_t es = (p->inc == SMRE_INC_BF16) ? 2 : (dt == SMRE_F64 ? 8 : 4);
+  const size_t xs = dt == SMRE_F64 ? 8 : 4;
+  cp->t.clear();
+  size_t off = 0;
+  for (int kk = 0; kk < pl.nsides; ++kk) {
+    const int k = p->order == SMRE_ORDER_ASC ? pl.nsides - 1 - kk : kk;  // sorted descending
+    const int sd = pl.sides[k];
+    for (int a = 0; a < sd; ++a)
+      for (int b = 0; b < sd; ++b) {
+        const int nr = (int)((H - a) / sd), nc = (int)((W - b) / sd);
+        if (nr <= 0 || nc <= 0) continue;
+        cp->t.push_back(CanonTiling{sd, a, b, nr, nc, k, off});
+        off = align_up(off + (size_t)nr * nc * sd * sd * es, 256);
+      }
+  }
+  cp->qbytes = off;
+  cp->off_prev = align_up(off, 256);
+  cp->off_isum = align_up(cp->off_prev + (size_t)H * W * xs, 256);
+  cp->off_sig = align_up(cp->off_isum + (size_t)H * W * xs, 256);
+  cp->total = align_up(cp->off_sig + kSigWords * sizeof(uint64_t), 256);
+  return SMRE_OK;
+}
+
+template <typename TX, typename TQ, int SMAX, bool KAHAN>
+void launch_tiling(const TilingArgs& g, hipStream_t s) {
+  const dim3 grid((unsigned)((g.nc + g.wpb - 1) / g.wpb), (unsigned)g.nr);
+  hipLaunchKernelGGL((tiling_phase<TX, TQ, SMAX, KAHAN>), grid, dim3(256), 0, s, g);
+}
+
+template <typename TX>
+int launch_tiling_any(int inc, int kahan, const TilingArgs& g, hipStream_t s) {
+  const bool big = g.s > 16;
+  if constexpr (sizeof(TX) == 8) {
+    big ? launch_tiling<double, double, 32, false>(g, s) : launch_tiling<double, double, 16, false>(g, s);
+  } else if (inc == SMRE_INC_BF16) {
+    if (kahan) big ? launch_tiling<float, bf16_t, 32, true>(g, s) : launch_tiling<float, bf16_t, 16, true>(g, s);
+    else big ? launch_tiling<float, bf16_t, 32, false>(g, s) : launch_tiling<float, bf16_t, 16, false>(g, s);
+  } else {
+    if (kahan) big ? launch_tiling<float, float, 32, true>(g, s) : launch_tiling<float, float, 16, true>(g, s);
+    else big ? launch_tiling<float, float, 32, false>(g, s) : launch_tiling<float, float, 16, false>(g, s);
+  }
+  HIP_OK(hipGetLastError());
+  return SMRE_OK;
+}
+
+template <typename TX>
+int canon_impl(smre_ctx* c, smre_dtype dt, void* x, int64_t H, int64_t W, int64_t ld,
+               const smre_params* p, const CanonPlan& cp, unsigned char* ws, hipStream_t s,
+               smre_report* rep) {
+  const Plan& pl = cp.base;
+  const size_t es = (p->inc == SMRE_INC_BF16) ? 2 : sizeof(TX);
+  HIP_OK(hipEventRecord(c->t0, s));
+  hipLaunchKernelGGL(ctrl_reset_kernel, dim3(1), dim3(1), 0, s, c->ctrl);
+  bool bad = false;
+  int rc = check_nonfinite<TX>(c, x, H, W, ld, s, &bad);
+  if (rc) return rc;
+  if (bad) return SMRE_ENONFINITE;
+  uint64_t sig[kSigWords];
+  problem_signature(dt, H, W, p, pl, sig);
+  sig[1] |= (uint64_t)p->order << 32;
+  sig[6] = (uint64_t)cp.qbytes;
+  TX* isum = (TX*)(ws + cp.off_isum);
+  uint64_t* dsig = (uint64_t*)(ws + cp.off_sig);
+  if (p->warm) {
+    uint64_t have[kSigWords];
+    HIP_OK(hipMemcpyAsync(have, dsig, sizeof have, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (std::memcmp(have, sig, sizeof sig) != 0) return SMRE_EINVAL;
+    hipLaunchKernelGGL((warm_begin_kernel<TX>), dim3(grid_rows(H)), dim3(256), 0, s, (TX*)x, ld,
+                       (int)H, (int)W, isum);
+  } else {
+    const int64_t nwords = (int64_t)(cp.qbytes / 4);
+    hipLaunchKernelGGL((fill_kernel<uint32_t>), dim3(grid_for(nwords)), dim3(256), 0, s,
+                       (uint32_t*)ws, nwords, 0u);
+    hipLaunchKernelGGL((keep_input_kernel<TX>), dim3(grid_rows(H)), dim3(256), 0, s,
+                       (const TX*)x, ld, (int)H, (int)W, isum);
+  }
+  hipLaunchKernelGGL((fill_kernel<uint64_t>), dim3(1), dim3(256), 0, s, dsig, (int64_t)kSigWords,
+                     (uint64_t)0);
+  HIP_OK(hipGetLastError());
+
+  TX* prev = (TX*)(ws + cp.off_prev);
+  const bool checking = p->tol > 0;
+  std::deque<std::pair<int, int>> inflight;  // (lag slot, sweep)
+  int lag_slot = 0, sweep = 0;
+  bool host_done = false;
+  int64_t launches = 0;
+  for (sweep = 1; sweep <= p->max_sweeps && !host_done; ++sweep) {
+    const bool check = checking && (sweep % p->check_every == 0 || sweep == p->max_sweeps);
+    if (check)
+      hipLaunchKernelGGL((snapshot_kernel<TX>), dim3(grid_rows(H)), dim3(256), 0, s,
+                         (const TX*)x, ld, (int)H, (int)W, prev, c->ctrl);
+    for (const CanonTiling& t : cp.t) {
+      TilingArgs g{};
+      g.x = x;
+      g.q = ws + t.off;
+      g.done = &c->ctrl->done;
+      g.ld = ld;
+      g.s = t.s;
+      g.a = t.a;
+      g.b = t.b;
+      g.nr = t.nr;
+      g.nc = t.nc;
+      g.wpb = 256 / t.s;
+      g.guard = (float)p->guard_rel;
+      g.r2f = (float)pl.r2[t.k];
+      g.rf = (float)std::sqrt(pl.r2[t.k]);
+      g.r2d = pl.r2[t.k];
+      if ((rc = launch_tiling_any<TX>(p->inc, p->kahan, g, s))) return rc;
+      ++launches;
+    }
+    if (check) {
+      hipLaunchKernelGGL((delta_kernel<TX>), dim3(grid_rows(H)), dim3(256), 0, s,
+                         (const TX*)x, ld, (int)H, (int)W, (const TX*)prev, c->ctrl);
+      hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(1), 0, s, c->ctrl, p->tol, sweep);
+      HIP_OK(hipGetLastError());
+      HIP_OK(hipMemcpyAsync(c->ctrl_host + 1 + lag_slot, c->ctrl, sizeof(Ctrl),
+                            hipMemcpyDeviceToHost, s));
+      HIP_OK(hipEventRecord(c->lag_ev[lag_slot], s));
+      inflight.push_back({lag_slot, sweep});
+      lag_slot = (lag_slot + 1) % (kLag + 1);
+      if ((int)inflight.size() > kLag) {
+        auto f = inflight.front();
+        inflight.pop_front();
+        HIP_OK(hipEventSynchronize(c->lag_ev[f.first]));
+        if (c->ctrl_host[1 + f.first].done) host_done = true;
+      }
+    }
+  }
+  hipLaunchKernelGGL((increment_sum_kernel<TX>), dim3(grid_rows(H)), dim3(256), 0, s,
+                     (const TX*)x, ld, (int)H, (int)W, isum);
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipStreamSynchronize(s));
+  HIP_OK(hipMemcpy(c->ctrl_host, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+  const Ctrl fin = *c->ctrl_host;
+  const int sweeps_run = fin.done ? fin.done_sweep : p->max_sweeps;
+  HIP_OK(hipMemcpy(dsig, sig, sizeof sig, hipMemcpyHostToDevice));
+  double viol = 0.0;
+  rc = run_violation<TX>(c, x, H, W, ld, pl.nsides, pl.sides, pl.r2, s, &viol);
+  if (rc) return rc;
+  HIP_OK(hipEventRecord(c->t1, s));
+  HIP_OK(hipEventSynchronize(c->t1));
+  float ms = 0.f;
+  HIP_OK(hipEventElapsedTime(&ms, c->t0, c->t1));
+  if (rep) {
+    rep->sweeps = sweeps_run;
+    rep->converged = fin.done;
+    rep->region = 0;
+    rep->inner_sweeps = 0;
+    rep->last_delta = checking ? fin.last_delta : NAN;
+    rep->max_violation = viol;
+    rep->elapsed_ms = ms;
+    rep->kernel_ms = 0.0;
+    rep->kernel_launches = launches;
     rep->bytes_moved = (double)sweeps_run * (2.0 * es * (double)pl.nq + 2.0 * sizeof(TX) * (double)H * W);
     rep->window_projections = (double)sweeps_run * (double)pl.nwin;
     rep->pixel_updates = (double)sweeps_run * (double)pl.nq;
@@ -2059,6 +2245,13 @@ int smre_paper_bounds(const int32_t* sides, int32_t n, double q, double* out) {
 int smre_workspace_size(smre_dtype dt, int64_t H, int64_t W, const smre_params* p,
                         size_t* bytes) {
   if (!bytes) return SMRE_EINVAL;
+  if (p && p->order != SMRE_ORDER_REGION) {
+    CanonPlan cp;
+    int rc = plan_canon(dt, H, W, p, &cp);
+    if (rc) return rc;
+    *bytes = cp.total;
+    return SMRE_OK;
+  }
   Plan pl;
   int rc = plan_project(dt, H, W, p, &pl, false);
   if (rc) return rc;
@@ -2072,27 +2265,34 @@ int smre_dykstra_project(smre_ctx* c, smre_dtype dt, void* x, int64_t H, int64_t
   if (!c || !x) return SMRE_EINVAL;
   if (ld < W) return SMRE_EINVAL;
   Plan pl;
-  int rc = plan_project(dt, H, W, p, &pl, true);
+  CanonPlan cp;
+  const bool canon = p && p->order != SMRE_ORDER_REGION;
+  int rc = canon ? plan_canon(dt, H, W, p, &cp) : plan_project(dt, H, W, p, &pl, true);
   if (rc) return rc;
+  const size_t total = canon ? cp.total : pl.total;
   rc = set_device(c);
   if (rc) return rc;
   unsigned char* ws = (unsigned char*)workspace;
   if (ws) {
-    if (ws_bytes < pl.total) return SMRE_ENOMEM;
+    if (ws_bytes < total) return SMRE_ENOMEM;
   } else {
-    if (c->ws_bytes < pl.total) {
+    if (c->ws_bytes < total) {
       if (c->ws) HIP_OK(hipFree(c->ws));
       c->ws = nullptr;
       c->ws_bytes = 0;
-      if (hipMalloc(&c->ws, pl.total) != hipSuccess) {
+      if (hipMalloc(&c->ws, total) != hipSuccess) {
         (void)hipGetLastError();
         return SMRE_ENOMEM;
       }
-      c->ws_bytes = pl.total;
+      c->ws_bytes = total;
     }
     ws = (unsigned char*)c->ws;
   }
   hipStream_t s = (hipStream_t)stream;
+  if (canon) {
+    if (dt == SMRE_F64) return canon_impl<double>(c, dt, x, H, W, ld, p, cp, ws, s, rep);
+    return canon_impl<float>(c, dt, x, H, W, ld, p, cp, ws, s, rep);
+  }
   if (dt == SMRE_F64) return project_impl<double>(c, dt, x, H, W, ld, p, pl, ws, s, rep);
   return project_impl<float>(c, dt, x, H, W, ld, p, pl, ws, s, rep);
 }
