@@ -59,6 +59,10 @@ def lib():
                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ip, ip,
                                         ip, dp, ctypes.POINTER(ctypes.c_int64)]
         L.oracle_icd_family.restype = ctypes.c_int
+        L.oracle_icd_nested.argtypes = [dp, i64, i64, ctypes.c_int32, ip, dp, ctypes.c_double,
+                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ip, ip,
+                                        ip, dp, ctypes.POINTER(ctypes.c_int64)]
+        L.oracle_icd_nested.restype = ctypes.c_int
         u64p = ctypes.POINTER(ctypes.c_uint64)
         L.oracle_philox4x64_10.argtypes = [u64p, u64p, u64p]
         L.oracle_philox4x64_10.restype = None
@@ -255,6 +259,30 @@ def icd_family(x0, K, r2, phases, tol=1e-13, mode=TOL_MAXABS, max_inner=100000):
                                  ctypes.byref(tot))
     if rc != 0:
         raise ValueError("oracle_icd_family rejected its arguments")
+    return z, tot.value
+
+
+def icd_nested(x0, level_sides, r2, phases, tol=1e-13, mode=TOL_MAXABS, max_inner=100000):
+    """ICD over a nested hierarchy of squares: level j has side level_sides[j]
+    (ascending, each dividing the next; blocks of the largest side), bound
+    r2[j]; phases = [(shift_y, shift_x, min_level), ...].  Returns
+    (z, total_inner_sweeps)."""
+    x0 = np.ascontiguousarray(x0, dtype=np.float64)
+    H, W = x0.shape
+    ls = np.ascontiguousarray(level_sides, dtype=np.int32)
+    r2 = np.ascontiguousarray(r2, dtype=np.float64)
+    if len(r2) != len(ls):
+        raise ValueError("need one bound per level")
+    sy = np.ascontiguousarray([p[0] for p in phases], dtype=np.int32)
+    sx = np.ascontiguousarray([p[1] for p in phases], dtype=np.int32)
+    lo = np.ascontiguousarray([p[2] for p in phases], dtype=np.int32)
+    z = np.empty_like(x0)
+    tot = ctypes.c_int64(0)
+    rc = lib().oracle_icd_nested(_d(x0), H, W, len(ls), _i(ls), _d(r2), float(tol), int(mode),
+                                 int(max_inner), len(phases), _i(sy), _i(sx), _i(lo), _d(z),
+                                 ctypes.byref(tot))
+    if rc != 0:
+        raise ValueError("oracle_icd_nested rejected its arguments")
     return z, tot.value
 
 

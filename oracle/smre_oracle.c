@@ -638,6 +638,98 @@ int oracle_icd_family(const double* x0, int64_t H, int64_t W, int32_t K, const d
   return 0;
 }
 
+/* ICD over a nested hierarchy of squares of any sides (Sec. 3.2 with the
+ * sides 2^k replaced by a divisor chain; Sec. 5 leaves the partition open).
+ *   side[j], j = 0..n_lev-1 : square side of level j, ascending, each dividing
+ *                             the next; the block side is B = side[n_lev-1]
+ *   r2[j]                   : bound of a square of level j
+ *   phase p                 : blocks of side B on the lattice shifted by
+ *                             (shift_y[p], shift_x[p]), 0 <= shift < B, clipped
+ *                             by the image edge; each block runs Dykstra over
+ *                             its level-j squares that lie inside the image,
+ *                             levels j = n_lev-1 down to min_level[p], with
+ *                             increments zeroed at the phase start
+ * The stopping rule and max_inner are those of oracle_icd_family; the paper's
+ * family is side[j] = 2^j, shifts 2^i mod 2^K, lowest level i. */
+int oracle_icd_nested(const double* x0, int64_t H, int64_t W, int32_t n_lev, const int32_t* side,
+                      const double* r2, double tol, int32_t mode, int32_t max_inner,
+                      int32_t n_phases, const int32_t* shift_y, const int32_t* shift_x,
+                      const int32_t* min_level, double* z, int64_t* inner_total) {
+  if (H < 1 || W < 1 || n_lev < 1 || n_lev > 16 || max_inner < 1 || n_phases < 1) return -1;
+  for (int j = 0; j < n_lev; ++j) {
+    if (side[j] < 1 || side[j] > 4096 || !(r2[j] > 0.0) || !isfinite(r2[j])) return -1;
+    if (j > 0 && (side[j] <= side[j - 1] || side[j] % side[j - 1] != 0)) return -1;
+  }
+  const int64_t B = side[n_lev - 1], HW = H * W;
+  for (int32_t ph = 0; ph < n_phases; ++ph)
+    if (shift_y[ph] < 0 || shift_y[ph] >= B || shift_x[ph] < 0 || shift_x[ph] >= B ||
+        min_level[ph] < 0 || min_level[ph] >= n_lev)
+      return -1;
+  /* one increment plane per level (a pixel lies in one square per level) */
+  double* inc = (double*)calloc((size_t)(n_lev * HW), sizeof(double));
+  double* ybuf = (double*)malloc((size_t)(B * B) * sizeof(double));
+  if (!inc || !ybuf) { free(inc); free(ybuf); return -1; }
+  if (z != x0) memcpy(z, x0, (size_t)HW * sizeof(double));
+  int64_t total = 0;
+  for (int32_t ph = 0; ph < n_phases; ++ph) {
+    const int lo = min_level[ph];
+#if ORACLE_MUTANT == 12
+    const int64_t oy = shift_y[ph] ? shift_y[ph] - B : 0, ox = shift_y[ph] ? shift_y[ph] - B : 0;
+#else
+    const int64_t oy = shift_y[ph] ? shift_y[ph] - B : 0, ox = shift_x[ph] ? shift_x[ph] - B : 0;
+#endif
+    for (int64_t by = oy; by < H; by += B)
+      for (int64_t bx = ox; bx < W; bx += B) {
+        const int64_t r0 = by > 0 ? by : 0, r1 = by + B < H ? by + B : H;
+        const int64_t c0 = bx > 0 ? bx : 0, c1 = bx + B < W ? bx + B : W;
+        const int64_t npix = (r1 - r0) * (c1 - c0);
+        for (int j = lo; j < n_lev; ++j)
+          for (int64_t i = r0; i < r1; ++i)
+            memset(inc + j * HW + i * W + c0, 0, (size_t)(c1 - c0) * sizeof(double));
+        for (int32_t it = 0; it < max_inner; ++it) {
+          double dsum = 0.0, dmax = 0.0;
+          for (int j = n_lev - 1 - (ORACLE_MUTANT == 11 && n_lev > 1); j >= lo; --j) {
+            const int64_t L = side[j];
+            double* I = inc + j * HW;
+            for (int64_t sy = by; sy < by + B; sy += L)
+              for (int64_t sx = bx; sx < bx + B; sx += L) {
+                if (sy < 0 || sx < 0 || sy + L > H || sx + L > W) continue;
+                /* Eq. (dykstra:if): y = x + I, x' = t y, I' = y - x' */
+                double n = 0.0;
+                int64_t c = 0;
+                for (int64_t i = sy; i < sy + L; ++i)
+                  for (int64_t q = sx; q < sx + L; ++q, ++c) {
+#if ORACLE_MUTANT == 13
+                    ybuf[c] = z[i * W + q] + I[(sy + q - sx) * W + sx + i - sy]; /* transposed */
+#else
+                    ybuf[c] = z[i * W + q] + I[i * W + q];
+#endif
+                    n += ybuf[c] * ybuf[c];
+                  }
+                const double t = n > r2[j] ? sqrt(r2[j] / n) : 1.0;
+                c = 0;
+                for (int64_t i = sy; i < sy + L; ++i)
+                  for (int64_t q = sx; q < sx + L; ++q, ++c) {
+                    const double xn = t * ybuf[c];
+                    const double d = fabs(z[i * W + q] - xn);
+                    dsum += d;
+                    if (d > dmax) dmax = d;
+                    I[i * W + q] = ybuf[c] - xn;
+                    z[i * W + q] = xn;
+                  }
+              }
+          }
+          ++total;
+          if (mode == ORACLE_TOL_MEANABS ? dsum <= tol * (double)npix : dmax < tol) break;
+        }
+      }
+  }
+  if (inner_total) *inner_total = total;
+  free(inc);
+  free(ybuf);
+  return 0;
+}
+
 /* The paper's ICD (Sec. 3.2): phases i = 0 .. num_phases - 1, both shifts
  * 2^i mod 2^K, lowest level i. */
 int oracle_icd(const double* x0, int64_t H, int64_t W, int32_t K, const double* r2, double tol,
