@@ -162,7 +162,8 @@ int smre_dykstra_project(smre_ctx* ctx, smre_dtype dtype, void* x, int64_t H, in
                          void* stream, smre_report* report);
 
 /* Incomplete Dykstra (Sec. 3.2), in place on x (device).
- *   K             block side 2^K (0 <= K <= 5); levels k = 0..K
+ *   K             block side 2^K (0 <= K <= 6; K = 6 runs on the nested-hierarchy
+ *                 kernel, smre_dykstra_incomplete_nested); levels k = 0..K
  *   radius2[K+1]  bound of a square of side 2^k
  *   tol, tolmode  block stopping rule after each inner sweep:
  *                 MAXABS: max |dx| < tol; MEANABS: sum |dx| <= tol * block pixels
@@ -227,6 +228,32 @@ int smre_dykstra_incomplete_family(smre_ctx* ctx, smre_dtype dtype, void* x, int
                                    const int32_t* shift_y, const int32_t* shift_x,
                                    const int32_t* min_level, double tol, int32_t tolmode,
                                    int32_t max_inner, void* stream, smre_report* report);
+
+/* The incomplete Dykstra over a nested hierarchy of squares of any sides
+ * (Sec. 3.2 with the sides 2^k replaced by a divisor chain; Sec. 5 names the
+ * partition of the image as the method's open choice): level j
+ * (0 <= j < n_levels <= 7) has squares of side level_side[j] (host array,
+ * ascending, each dividing the next, at most 96) bounded by radius2[j]; the
+ * block side is B = level_side[n_levels - 1].  Phase p uses blocks of side B
+ * on the lattice shifted by (shift_y[p], shift_x[p]) (0 <= shift < B; blocks
+ * cut by the image edge are clipped) and projects each block onto its squares
+ * of the levels n_levels - 1 down to min_level[p] that lie inside the image, by
+ * Dykstra with increments zeroed at the phase start, until the block meets the
+ * stopping rule (as smre_dykstra_incomplete).  One workgroup per block: the
+ * chain needs a level whose squares hold at most 16 pixels, with B^2 / that
+ * many <= 1024 (<= 512 for 9 pixels, <= 256 for 16); SMRE_EINVAL otherwise
+ * (so 1, 2, ..., 64, and 1, 3, 6, 12, 24, 48 run; 1, 5, 10, 20, 40 does not).
+ * The chain 1, 2, ..., 2^K with shifts 2^i mod 2^K and lowest level i is the
+ * paper's ICD; smre_dykstra_incomplete with K = 6 runs here.  Frames, report
+ * and return codes as smre_dykstra_incomplete_family (max_violation over every
+ * window of the levels' sides). */
+int smre_dykstra_incomplete_nested(smre_ctx* ctx, smre_dtype dtype, void* x, int64_t H,
+                                   int64_t W, int64_t ld, int64_t frames, int32_t n_levels,
+                                   const int32_t* level_side, const double* radius2,
+                                   int32_t n_phases, const int32_t* shift_y,
+                                   const int32_t* shift_x, const int32_t* min_level, double tol,
+                                   int32_t tolmode, int32_t max_inner, void* stream,
+                                   smre_report* report);
 
 /* ---- Batches: images of different sizes in one persistent launch per colour ----
  * Each image carries its own sides, bounds, tolerance and sweep cap; the

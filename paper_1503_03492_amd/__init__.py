@@ -132,6 +132,9 @@ def _load():
     L.smre_dykstra_incomplete_family.argtypes = [vp, ctypes.c_int, vp, i64, i64, i64, i64, i32,
                                                  dp, i32, ip, ip, ip, dbl, i32, i32, vp,
                                                  ctypes.POINTER(Report)]
+    L.smre_dykstra_incomplete_nested.argtypes = [vp, ctypes.c_int, vp, i64, i64, i64, i64, i32,
+                                                 ip, dp, i32, ip, ip, ip, dbl, i32, i32, vp,
+                                                 ctypes.POINTER(Report)]
     L.smre_max_violation.argtypes = [vp, ctypes.c_int, vp, i64, i64, i64, i32, ip, dp, vp, dp]
     L.smre_batch_workspace_size.argtypes = [ctypes.c_int, i32, ctypes.POINTER(BatchImage),
                                             ctypes.POINTER(BatchParams),
@@ -167,6 +170,7 @@ EXPORTS = ["smre_status_string", "smre_ctx_create", "smre_ctx_destroy", "smre_ct
            "smre_chi2_bounds", "smre_paper_bounds", "smre_workspace_size",
            "smre_dykstra_project", "smre_dykstra_incomplete", "smre_dykstra_incomplete_frames",
            "smre_dykstra_incomplete_family", "smre_dykstra_incomplete_noalloc",
+           "smre_dykstra_incomplete_nested",
            "smre_max_violation",
            "smre_batch_workspace_size", "smre_dykstra_project_batch", "smre_serve_create",
            "smre_serve_destroy", "smre_serve_submit", "smre_serve_poll", "smre_serve_stats",
@@ -180,6 +184,18 @@ def lib():
 
 def status_string(code):
     return _lib.smre_status_string(int(code)).decode()
+
+
+def _frames(x):
+    """(frames, H, W, ld) of a 2-D image or an (n, H, W) stack of frames."""
+    import torch
+    if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dim() not in (2, 3):
+        raise TypeError("x must be a 2-D or 3-D CUDA tensor")
+    if x.dim() == 2:
+        return (1,) + tuple(_image(x))
+    if x.stride(2) != 1 or x.stride(0) != x.shape[1] * x.stride(1):
+        raise ValueError("frames must be stacked at stride H * ld")
+    return x.shape[0], x.shape[1], x.shape[2], x.stride(1)
 
 
 def _check(code, what, allow=(OK,)):
@@ -379,15 +395,7 @@ class Context:
                           max_inner=10000, stream=None):
         """ICD over a phase family [(shift_y, shift_x, min_level), ...] on x, a 2-D
         image or an (n, H, W) stack of frames (CUDA tensor), in place."""
-        import torch
-        if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dim() not in (2, 3):
-            raise TypeError("x must be a 2-D or 3-D CUDA tensor")
-        if x.dim() == 2:
-            n, (H, W, ld) = 1, _image(x)
-        else:
-            if x.stride(2) != 1 or x.stride(0) != x.shape[1] * x.stride(1):
-                raise ValueError("frames must be stacked at stride H * ld")
-            n, H, W, ld = x.shape[0], x.shape[1], x.shape[2], x.stride(1)
+        n, H, W, ld = _frames(x)
         r, rp = _dvec(radius2)
         if len(r) != K + 1:
             raise ValueError("radius2 needs K+1 entries")
@@ -401,6 +409,29 @@ class Context:
                                                  int(mode), int(max_inner), _stream(stream),
                                                  ctypes.byref(rep))
         _check(rc, "smre_dykstra_incomplete_family", allow=(OK, NOT_CONVERGED))
+        return rep.as_dict()
+
+    def incomplete_nested(self, x, level_sides, radius2, phases, tol=1e-3, mode=TOL_MEANABS,
+                          max_inner=10000, stream=None):
+        """ICD over a nested hierarchy of squares: level j has side
+        level_sides[j] (ascending, each dividing the next) and bound
+        radius2[j]; phases = [(shift_y, shift_x, min_level), ...].  x is a 2-D
+        image or an (n, H, W) stack of frames (CUDA tensor), in place."""
+        n, H, W, ld = _frames(x)
+        ls, lsp = _ivec(level_sides)
+        r, rp = _dvec(radius2)
+        if len(r) != len(ls):
+            raise ValueError("radius2 needs one entry per level")
+        sy, syp = _ivec([p[0] for p in phases])
+        sx, sxp = _ivec([p[1] for p in phases])
+        lo, lop = _ivec([p[2] for p in phases])
+        rep = Report()
+        rc = _lib.smre_dykstra_incomplete_nested(self._h, _dtype_code(x),
+                                                 ctypes.c_void_p(x.data_ptr()), H, W, ld, n,
+                                                 len(ls), lsp, rp, len(sy), syp, sxp, lop,
+                                                 float(tol), int(mode), int(max_inner),
+                                                 _stream(stream), ctypes.byref(rep))
+        _check(rc, "smre_dykstra_incomplete_nested", allow=(OK, NOT_CONVERGED))
         return rep.as_dict()
 
     def project_batch(self, xs, sides, radius2, tol=1e-5, max_sweeps=5000, region=0,

@@ -104,8 +104,11 @@ __global__ __launch_bounds__(256) void nonfinite_kernel(const TX* x, int64_t ld,
 // (VT + s - 1) x (VW + s - 1) pixels in LDS, sums each row over s columns,
 // then those row sums over s rows (O(s) adds per window instead of s^2 loads).
 // blockIdx.z selects a frame of a movie (frames fstride elements apart).
+// Tiles of 32 x 64 anchors for sides up to 33, 16 x 32 up to 65.
 constexpr int kViolTileH = 32, kViolTileW = 64, kViolMaxSide = 33;
-template <typename TX>
+constexpr int kViolTileH2 = 16, kViolTileW2 = 32, kViolMaxSide2 = 65;
+template <typename TX, int kViolTileH = smre::kViolTileH, int kViolTileW = smre::kViolTileW,
+          int kViolMaxSide = smre::kViolMaxSide>
 __global__ __launch_bounds__(256) void violation_kernel(const TX* x, int64_t fstride, int64_t ld,
                                                         int H, int W, int s, double r2,
                                                         Ctrl* ctrl) {

@@ -28,6 +28,7 @@
 #include "kernels.hpp"
 #include "mc.hpp"
 #include "canon.hpp"
+#include "icd_nested.hpp"
 #include "admm.hpp"
 #include "serve_core.hpp"
 #include "smre.h"
@@ -399,11 +400,19 @@ int run_violation(smre_ctx* c, const void* x, int64_t H, int64_t W, int64_t ld, 
     const unsigned nz = (unsigned)std::min<int64_t>(65535, frames - f0);
     const TX* xf = (const TX*)x + f0 * H * ld;
     for (int k = 0; k < n; ++k) {
-      if (sides[k] > kViolMaxSide) return SMRE_EINVAL;
-      const dim3 grid((unsigned)((W - sides[k] + kViolTileW) / kViolTileW),
-                      (unsigned)((H - sides[k] + kViolTileH) / kViolTileH), nz);
-      hipLaunchKernelGGL((violation_kernel<TX>), grid, dim3(256), 0, s, xf, H * ld, ld, (int)H,
-                         (int)W, sides[k], r2[k], c->ctrl);
+      if (sides[k] > kViolMaxSide2) return SMRE_EINVAL;
+      if (sides[k] <= kViolMaxSide) {
+        const dim3 grid((unsigned)((W - sides[k] + kViolTileW) / kViolTileW),
+                        (unsigned)((H - sides[k] + kViolTileH) / kViolTileH), nz);
+        hipLaunchKernelGGL((violation_kernel<TX>), grid, dim3(256), 0, s, xf, H * ld, ld,
+                           (int)H, (int)W, sides[k], r2[k], c->ctrl);
+      } else {
+        const dim3 grid((unsigned)((W - sides[k] + kViolTileW2) / kViolTileW2),
+                        (unsigned)((H - sides[k] + kViolTileH2) / kViolTileH2), nz);
+        hipLaunchKernelGGL((violation_kernel<TX, kViolTileH2, kViolTileW2, kViolMaxSide2>), grid,
+                           dim3(256), 0, s, xf, H * ld, ld, (int)H, (int)W, sides[k], r2[k],
+                           c->ctrl);
+      }
     }
   }
   HIP_OK(hipGetLastError());
@@ -965,6 +974,209 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t fra
     rep->elapsed_ms = ms;
     rep->kernel_ms = tacc ? tacc->ms : 0.0;
     rep->kernel_launches = tacc ? tacc->launches : 0;
+    rep->bytes_moved = 2.0 * sizeof(T) * (double)H * W * nph * (double)frames;
+    rep->window_projections = (double)sums[1];
+    rep->pixel_updates = (double)sums[2];
+  }
+  return sums[3] == 0 ? SMRE_OK : SMRE_NOT_CONVERGED;
+}
+
+// ---------------------------------------------------------------- nested ICD
+// Lane layout of a divisor chain (icd_nested.hpp): the lane level m is the
+// finest-grained level whose squares hold at most 16 pixels while the block
+// still fits the lanes the kernel instance allows.
+int nested_lanes_max(int P) { return P == 16 ? 256 : P == 9 ? 512 : 1024; }
+
+int nested_tables(int nlev, const int32_t* side, NestedArgs* a) {
+  const int B = side[nlev - 1];
+  int m = -1;
+  for (int j = 0; j < nlev; ++j) {
+    const int P = side[j] * side[j];
+    if (P <= 16 && B * B / P <= nested_lanes_max(P)) m = j;
+  }
+  if (m < 0) return SMRE_EINVAL;
+  const int P = side[m] * side[m];
+  a->B = B;
+  a->nlev = nlev;
+  a->m = m;
+  a->nt = B * B / P;
+  for (int j = 0; j < kNestLevels; ++j) {
+    a->side[j] = j < nlev ? side[j] : 0;
+    a->rad[j] = (j >= 1 && j < nlev) ? side[j] / side[j - 1] : 1;
+    a->grp[j] = (j > m && j < nlev) ? (side[j] / side[m]) * (side[j] / side[m]) : 1;
+    a->rstart[j] = a->rend[j] = 0;
+    if (j <= m) {
+      const int A = side[j] * side[j];
+      for (int e = 0; e < P; ++e) {
+        if (e % A == 0) a->rstart[j] |= 1u << e;
+        if (e % A == A - 1) a->rend[j] |= 1u << e;
+      }
+    }
+  }
+  // element e of a lane: its digits, lowest first -- the pixel inside its
+  // level-0 square (raster), then the sub-square at each level up to m
+  for (int e = 0; e < 16; ++e) {
+    int r = 0, c = 0;
+    if (e < P) {
+      int u = e;
+      const int a0 = side[0] * side[0];
+      const int d0 = u % a0;
+      u /= a0;
+      r = d0 / side[0];
+      c = d0 % side[0];
+      for (int j = 1; j <= m; ++j) {
+        const int rd = side[j] / side[j - 1], rr = rd * rd;
+        const int d = u % rr;
+        u /= rr;
+        r += (d / rd) * side[j - 1];
+        c += (d % rd) * side[j - 1];
+      }
+    }
+    a->pr[e] = (uint8_t)r;
+    a->pc[e] = (uint8_t)c;
+    for (int j = 0; j < kNestLevels; ++j) {
+      const int L = (j <= m) ? side[j] : 1;
+      a->sqr[j][e] = (uint8_t)((r / L) * L);
+      a->sqc[j][e] = (uint8_t)((c / L) * L);
+    }
+  }
+  return SMRE_OK;
+}
+
+template <typename T, bool MEANABS>
+void launch_nested(int P, dim3 grid, int threads, const NestedArgs& a, hipStream_t s) {
+  switch (P) {
+    case 16: hipLaunchKernelGGL((icd_nested_phase<T, 16, MEANABS>), grid, dim3(threads), 0, s, a); break;
+    case 9: hipLaunchKernelGGL((icd_nested_phase<T, 9, MEANABS>), grid, dim3(threads), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((icd_nested_phase<T, 4, MEANABS>), grid, dim3(threads), 0, s, a); break;
+    default: hipLaunchKernelGGL((icd_nested_phase<T, 1, MEANABS>), grid, dim3(threads), 0, s, a); break;
+  }
+}
+
+int nested_validate(smre_ctx* c, smre_dtype dt, const void* x, int64_t H, int64_t W, int64_t ld,
+                    int64_t frames, int32_t nlev, const int32_t* side, const double* r2,
+                    int32_t n_phases, const int32_t* shift_y, const int32_t* shift_x,
+                    const int32_t* min_level, double tol, int32_t mode, int32_t max_inner) {
+  if (!c || !x || !side || !r2 || !shift_y || !shift_x || !min_level) return SMRE_EINVAL;
+  if (frames < 1 || frames * H > INT32_MAX) return SMRE_EINVAL;
+  if (dt != SMRE_F32 && dt != SMRE_F64) return SMRE_EINVAL;
+  if (H < 1 || W < 1 || ld < W || H > (1 << 20) || W > (1 << 20)) return SMRE_EINVAL;
+  if (nlev < 1 || nlev > kNestLevels || max_inner < 1 || n_phases < 1 || n_phases > 64)
+    return SMRE_EINVAL;
+  for (int j = 0; j < nlev; ++j) {
+    if (side[j] < 1 || side[j] > 96) return SMRE_EINVAL;
+    if (j > 0 && (side[j] <= side[j - 1] || side[j] % side[j - 1] != 0)) return SMRE_EINVAL;
+    if (!std::isfinite(r2[j])) return SMRE_ENONFINITE;
+    if (!(r2[j] > 0)) return SMRE_EINVAL;
+  }
+  const int B = side[nlev - 1];
+  {
+    const int64_t nbx = W / B + 2, nby = H / B + 2;
+    if (nbx * nby >= ((int64_t)1 << 31)) return SMRE_EINVAL;
+  }
+  for (int p = 0; p < n_phases; ++p)
+    if (shift_y[p] < 0 || shift_y[p] >= B || shift_x[p] < 0 || shift_x[p] >= B ||
+        min_level[p] < 0 || min_level[p] >= nlev)
+      return SMRE_EINVAL;
+  if (mode != SMRE_TOL_MAXABS && mode != SMRE_TOL_MEANABS) return SMRE_EINVAL;
+  if (!std::isfinite(tol)) return SMRE_EINVAL;
+  NestedArgs a{};
+  return nested_tables(nlev, side, &a);
+}
+
+template <typename T>
+int nested_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t frames, int nlev,
+                const int32_t* side, const double* r2, double tol, int mode, int max_inner,
+                int nph, const int32_t* sy, const int32_t* sx, const int32_t* lo, hipStream_t s,
+                smre_report* rep) {
+  HIP_OK(hipEventRecord(c->t0, s));
+  hipLaunchKernelGGL(ctrl_reset_kernel, dim3(1), dim3(1), 0, s, c->ctrl);
+  bool bad = false;
+  int rc = check_nonfinite<T>(c, x, frames * H, W, ld, s, &bad);
+  if (rc) return rc;
+  if (bad) return SMRE_ENONFINITE;
+  if (!c->icd_cnt)
+    HIP_OK(hipMalloc(&c->icd_cnt, sizeof(unsigned long long) * (kIcdCntWords + 8)));
+  unsigned long long* cnt = c->icd_cnt;
+  unsigned long long* cnt_sum = c->icd_cnt + kIcdCntWords;
+  hipLaunchKernelGGL((fill_kernel<unsigned long long>), dim3(grid_for(kIcdCntWords)), dim3(256),
+                     0, s, cnt, kIcdCntWords, 0ull);
+  NestedArgs a{};
+  rc = nested_tables(nlev, side, &a);
+  if (rc) return rc;
+  const int P = side[a.m] * side[a.m];
+  const int threads = (a.nt + 63) / 64 * 64;
+  a.ld = ld;
+  a.fstride = H * ld;
+  a.H = (int)H;
+  a.W = (int)W;
+  a.mode = mode;
+  a.max_inner = max_inner;
+  a.tol = tol;
+  for (int j = 0; j < nlev; ++j) {
+    a.r2[j] = r2[j];
+    a.sr2[j] = std::sqrt((float)r2[j]);
+  }
+  a.counters = cnt;
+  const int B = a.B;
+  TimingAcc tacc;
+  for (int ph = 0; ph < nph; ++ph) {
+    a.oy = sy[ph] > 0 ? sy[ph] - B : 0;
+    a.ox = sx[ph] > 0 ? sx[ph] - B : 0;
+    a.lo = lo[ph];
+    const int nby = (int)((H - a.oy + B - 1) / B), nbx = (int)((W - a.ox + B - 1) / B);
+    a.nbx = nbx;
+    int slot = -1;
+    if ((rc = timing_begin(c, tacc, s, &slot))) return rc;
+    for (int64_t f0 = 0; f0 < frames; f0 += 65535) {
+      const int64_t nf = std::min<int64_t>(65535, frames - f0);
+      a.x = (T*)x + f0 * H * ld;
+      const dim3 grid((unsigned)(nbx * nby), (unsigned)nf);
+      if (mode == SMRE_TOL_MEANABS)
+        launch_nested<T, true>(P, grid, threads, a, s);
+      else
+        launch_nested<T, false>(P, grid, threads, a, s);
+      HIP_OK(hipGetLastError());
+    }
+    if ((rc = timing_end(c, tacc, s, slot))) return rc;
+  }
+  hipLaunchKernelGGL(icd_counter_sum, dim3(1), dim3(kIcdSlots), 0, s, cnt, cnt_sum);
+  HIP_OK(hipGetLastError());
+  unsigned long long sums[kIcdCountWords];
+  HIP_OK(hipMemcpyAsync(sums, cnt_sum, sizeof sums, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  if ((rc = timing_flush(c, tacc, true))) return rc;
+  // reported: the violation over the full family of the levels' sides (every
+  // position, every frame)
+  double viol = NAN;
+  if (rep) {
+    int fam[kNestLevels];
+    double fam_r2[kNestLevels];
+    int nfam = 0;
+    for (int j = 0; j < nlev; ++j)
+      if (side[j] <= H && side[j] <= W) {
+        fam[nfam] = side[j];
+        fam_r2[nfam++] = r2[j];
+      }
+    if (nfam > 0) {
+      rc = run_violation<T>(c, x, H, W, ld, nfam, fam, fam_r2, s, &viol, frames);
+      if (rc) return rc;
+    }
+  }
+  HIP_OK(hipEventRecord(c->t1, s));
+  HIP_OK(hipEventSynchronize(c->t1));
+  float ms = 0.f;
+  HIP_OK(hipEventElapsedTime(&ms, c->t0, c->t1));
+  if (rep) {
+    rep->sweeps = nph;
+    rep->converged = sums[3] == 0;
+    rep->region = B;
+    rep->inner_sweeps = (int32_t)std::min<unsigned long long>(sums[0], INT32_MAX);
+    rep->last_delta = NAN;
+    rep->max_violation = viol;
+    rep->elapsed_ms = ms;
+    rep->kernel_ms = tacc.ms;
+    rep->kernel_launches = tacc.launches;
     rep->bytes_moved = 2.0 * sizeof(T) * (double)H * W * nph * (double)frames;
     rep->window_projections = (double)sums[1];
     rep->pixel_updates = (double)sums[2];
@@ -2308,8 +2520,8 @@ int smre_dykstra_incomplete_frames(smre_ctx* c, smre_dtype dt, void* x, int64_t 
                                    int64_t ld, int64_t frames, int32_t K, const double* r2,
                                    double tol, int32_t mode, int32_t max_inner, int32_t nph,
                                    void* stream, smre_report* rep) {
-  if (K < 0 || K > 5 || nph < 1 || nph > K + 1) return SMRE_EINVAL;
-  int32_t sy[6], sx[6], lo[6];
+  if (K < 0 || K > 6 || nph < 1 || nph > K + 1) return SMRE_EINVAL;
+  int32_t sy[7], sx[7], lo[7];
   for (int i = 0; i < nph; ++i) {
     sy[i] = sx[i] = (1 << i) & ((1 << K) - 1);
     lo[i] = i;
@@ -2324,6 +2536,15 @@ int smre_dykstra_incomplete_family(smre_ctx* c, smre_dtype dt, void* x, int64_t 
                                    const int32_t* shift_x, const int32_t* min_level, double tol,
                                    int32_t mode, int32_t max_inner, void* stream,
                                    smre_report* rep) {
+  if (K == 6) {
+    // 64 x 64 blocks exceed one wave's registers: the nested-hierarchy kernel
+    // with the chain 1, 2, ..., 64 runs them
+    if (!r2) return SMRE_EINVAL;
+    const int32_t chain[7] = {1, 2, 4, 8, 16, 32, 64};
+    return smre_dykstra_incomplete_nested(c, dt, x, H, W, ld, frames, 7, chain, r2, n_phases,
+                                          shift_y, shift_x, min_level, tol, mode, max_inner,
+                                          stream, rep);
+  }
   int rc = icd_validate(c, dt, x, H, W, ld, frames, K, r2, n_phases, shift_y, shift_x, min_level,
                         tol, mode, max_inner);
   if (rc) return rc;
@@ -2335,6 +2556,25 @@ int smre_dykstra_incomplete_family(smre_ctx* c, smre_dtype dt, void* x, int64_t 
                             shift_y, shift_x, min_level, s, rep);
   return icd_impl<float>(c, x, H, W, ld, frames, K, r2, tol, mode, max_inner, n_phases, shift_y,
                          shift_x, min_level, s, rep);
+}
+
+int smre_dykstra_incomplete_nested(smre_ctx* c, smre_dtype dt, void* x, int64_t H, int64_t W,
+                                   int64_t ld, int64_t frames, int32_t n_levels,
+                                   const int32_t* level_side, const double* r2, int32_t n_phases,
+                                   const int32_t* shift_y, const int32_t* shift_x,
+                                   const int32_t* min_level, double tol, int32_t mode,
+                                   int32_t max_inner, void* stream, smre_report* rep) {
+  int rc = nested_validate(c, dt, x, H, W, ld, frames, n_levels, level_side, r2, n_phases,
+                           shift_y, shift_x, min_level, tol, mode, max_inner);
+  if (rc) return rc;
+  rc = set_device(c);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (dt == SMRE_F64)
+    return nested_impl<double>(c, x, H, W, ld, frames, n_levels, level_side, r2, tol, mode,
+                               max_inner, n_phases, shift_y, shift_x, min_level, s, rep);
+  return nested_impl<float>(c, x, H, W, ld, frames, n_levels, level_side, r2, tol, mode,
+                            max_inner, n_phases, shift_y, shift_x, min_level, s, rep);
 }
 
 int smre_dykstra_incomplete_noalloc(smre_ctx* c, smre_dtype dt, void* x, int64_t H, int64_t W,
