@@ -366,6 +366,35 @@ def bench_icd(args):
            "inner_sweeps": reps[-1]["inner_sweeps"], "phase_kernel_ms": kms / args.steps,
            "hbm_GBps": by / (kms * 1e-3) / 1e9 if kms else None,
            "max_violation_full_family": reps[-1]["max_violation"]}
+
+    # the same image through the nested-hierarchy kernel (one workgroup per
+    # block): K = 6 of the paper's family, and a chain of sides 1, 3, ..., 48
+    def variant(run):
+        for _ in range(max(1, args.warmup)):
+            x.copy_(d)
+            run(x)
+        torch.cuda.synchronize()
+        rs = []
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            x.copy_(d)
+            rs.append(run(x))
+        torch.cuda.synchronize()
+        e = time.perf_counter() - t1
+        return {"ms": e / args.steps * 1e3,
+                "phase_kernel_ms": sum(r["kernel_ms"] for r in rs) / args.steps,
+                "inner_sweeps": rs[-1]["inner_sweeps"],
+                "window_projections_per_s": sum(r["window_projections"] for r in rs) / e,
+                "max_violation_full_family": rs[-1]["max_violation"]}
+
+    r6 = smre.chi2_bounds([1 << k for k in range(7)])
+    out["K6"] = variant(lambda t: ctx.incomplete(t, 6, r6, tol=1e-3, mode=smre.TOL_MEANABS,
+                                                 max_inner=10000))
+    ch = [1, 3, 6, 12, 24, 48]
+    rc_ = smre.chi2_bounds(ch)
+    out["chain_1_3_6_12_24_48"] = variant(
+        lambda t: ctx.incomplete_nested(t, ch, rc_, nested_paper_phases(ch), tol=1e-3,
+                                        mode=smre.TOL_MEANABS, max_inner=10000))
     print(json.dumps(out), flush=True)
 
 
@@ -569,6 +598,14 @@ def icd_offdiagonal_phases(K):
     return out
 
 
+def nested_paper_phases(sides):
+    """The paper's phase pattern on a divisor chain: phase i shifted by
+    side[i] mod B on both axes, levels n-1..i (for 1, 2, ..., 2^K it is the
+    paper's family)."""
+    B = sides[-1]
+    return [(sides[i] % B, sides[i] % B, i) for i in range(len(sides))]
+
+
 def bench_admm(args):
     """The paper's timing experiment: 100 ADMM iterations on a 512^2 deblurring
     problem (synthetic piecewise-smooth scene standing in for the test image,
@@ -641,7 +678,9 @@ def bench_full_vs_icd(args):
     1e-5) against the incomplete Dykstra (K = 3: squares of side 1, 2, 4, 8;
     mean-abs inner tolerance 1e-3) with the paper's 4 phases and with a family
     that adds phases shifted along one axis only (10 phases).  Reported, not
-    gated (the paper states only that the two are nearly identical): relative
+    gated (the paper states only that the two are nearly identical), and two
+    nested hierarchies off the powers of two (squares of side 1, 3, 6 with the
+    paper's phase pattern; that after the paper's K = 3 phases): relative
     L2 and max-abs distance to the full solution, Fourier ring correlation with
     it, the share of full-family windows left violated and the worst violation
     ratio, and each method's time."""
@@ -663,15 +702,35 @@ def bench_full_vs_icd(args):
     rk = smre.chi2_bounds([1 << k for k in range(K + 1)])
     B = 1 << K
 
-    def compare(phases):
+    def family(phases):
+        def run(xi):
+            return ctx.incomplete_family(xi, K, rk, phases, tol=1e-3, mode=smre.TOL_MEANABS,
+                                         max_inner=10000)
+        return run, len(phases)
+
+    def nested(chains):
+        # one or more hierarchies applied in turn, each with its phase list
+        def run(xi):
+            tot = None
+            for ch, ph in chains:
+                r = ctx.incomplete_nested(xi, ch, smre.chi2_bounds(ch), ph, tol=1e-3,
+                                          mode=smre.TOL_MEANABS, max_inner=10000)
+                if tot is None:
+                    tot = dict(r)
+                else:
+                    for k in ("inner_sweeps", "window_projections"):
+                        tot[k] += r[k]
+            return tot
+        return run, sum(len(ph) for _, ph in chains)
+
+    def compare(spec):
+        runner, nph = spec
         xi = torch.from_numpy(x0).cuda()
-        ctx.incomplete_family(xi, K, rk, phases, tol=1e-3, mode=smre.TOL_MEANABS,
-                              max_inner=10000)   # warm-up, then timed
+        runner(xi)   # warm-up, then timed
         xi = torch.from_numpy(x0).cuda()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        irep = ctx.incomplete_family(xi, K, rk, phases, tol=1e-3, mode=smre.TOL_MEANABS,
-                                     max_inner=10000)
+        irep = runner(xi)
         torch.cuda.synchronize()
         t_icd = time.perf_counter() - t0
         zi = xi.double().cpu().numpy()
@@ -683,7 +742,7 @@ def bench_full_vs_icd(args):
             viol += int(np.sum(w > r * (1 + 1e-6)))
             worst = max(worst, float(np.max(w / r)))
             total += w.size
-        return {"phases": len(phases), "ms": t_icd * 1e3,
+        return {"phases": nph, "ms": t_icd * 1e3,
                 "inner_sweeps": irep["inner_sweeps"],
                 "window_projections": irep["window_projections"],
                 "rel_l2_to_full": float(np.linalg.norm(zi - zf) / np.linalg.norm(zf)),
@@ -692,8 +751,13 @@ def bench_full_vs_icd(args):
                 "violated_window_share": viol / total, "worst_violation_ratio": worst,
                 "speedup_over_full": t_full / t_icd}
 
-    paper = compare([((1 << i) % B, (1 << i) % B, i) for i in range(K + 1)])
-    offd = compare(icd_offdiagonal_phases(K))
+    paper = compare(family([((1 << i) % B, (1 << i) % B, i) for i in range(K + 1)]))
+    offd = compare(family(icd_offdiagonal_phases(K)))
+    c136 = [1, 3, 6]
+    chain = compare(nested([(c136, nested_paper_phases(c136))]))
+    both = compare(nested([([1 << k for k in range(K + 1)],
+                            [((1 << i) % B, (1 << i) % B, i) for i in range(K + 1)]),
+                           (c136, nested_paper_phases(c136))]))
     out = {"metric": "full vs incomplete Dykstra (512^2, sides 1..8 vs K=3)",
            "value": paper["rel_l2_to_full"], "unit": "relative L2 distance", "n_gpus": 1,
            "steps": 1, "warmup": 0, "ms_per_step": (t_full * 1e3 + paper["ms"] + offd["ms"]),
@@ -701,7 +765,8 @@ def bench_full_vs_icd(args):
            "data": "synthetic", "config": {"workload": "full_vs_icd_512sq"},
            "full": {"sweeps": rep["sweeps"], "converged": rep["converged"], "ms": t_full * 1e3,
                     "max_violation": rep["max_violation"]},
-           "icd_paper_phases": paper, "icd_offdiagonal_phases": offd}
+           "icd_paper_phases": paper, "icd_offdiagonal_phases": offd,
+           "icd_chain_1_3_6": chain, "icd_chains_1_2_4_8_then_1_3_6": both}
     print(json.dumps(out), flush=True)
 
 

@@ -982,18 +982,25 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t fra
 }
 
 // ---------------------------------------------------------------- nested ICD
-// Lane layout of a divisor chain (icd_nested.hpp): the lane level m is the
-// finest-grained level whose squares hold at most 16 pixels while the block
-// still fits the lanes the kernel instance allows.
+// Lane layout of a divisor chain (icd_nested.hpp): the lane level m is one
+// whose squares hold at most 16 pixels while the block fits the lanes the
+// kernel instance allows.  Of those, the one with the fewest lanes that still
+// fills a wave (fewer reduction steps per inner sweep), else the one with the
+// most lanes (small blocks: as many busy lanes as the block has).  The choice
+// depends on the chain only, so a frame gives the same bits alone or in a
+// movie.
 int nested_lanes_max(int P) { return P == 16 ? 256 : P == 9 ? 512 : 1024; }
 
 int nested_tables(int nlev, const int32_t* side, NestedArgs* a) {
   const int B = side[nlev - 1];
-  int m = -1;
-  for (int j = 0; j < nlev; ++j) {
+  int m = -1, m_most = -1;
+  for (int j = nlev - 1; j >= 0; --j) {
     const int P = side[j] * side[j];
-    if (P <= 16 && B * B / P <= nested_lanes_max(P)) m = j;
+    if (P > 16 || B * B / P > nested_lanes_max(P)) continue;
+    m_most = j;                           // ends at the most lanes
+    if (m < 0 && B * B / P >= 64) m = j;  // first (fewest lanes) filling a wave
   }
+  if (m < 0) m = m_most;
   if (m < 0) return SMRE_EINVAL;
   const int P = side[m] * side[m];
   a->B = B;

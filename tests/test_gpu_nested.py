@@ -2,10 +2,11 @@
 smre_dykstra_incomplete with K = 6) against oracle_icd_nested.
 
 Chains cover every lane layout of the kernel: 16 pixels per lane (1, 2, ...,
-64), 9 (1, 3, 6, 12, 24, 48; 1, 3, 9, 27), 4 (1, 2, 6, 12; 2, 6, 12 whose finest
-square holds 4 pixels) and 1 (1, 5, 10); cross-lane groups by butterflies (4,
-16, 64 lanes) and by the LDS tree (9, 25, 36, 100, 256 lanes); one-level
-chains; ragged images and shifted lattices on each axis.
+64; 4, 8, ..., 64; 4), 9 (1, 3, 6, 12, 24, 48; 1, 3, 9, 27; 3), 4 (2, 6, 12,
+whose finest square holds 4 pixels) and 1 (1, 2, 6, 12; 1, 5, 10); cross-lane
+groups by butterflies (4, 16, 64 lanes) and by the LDS tree (9, 25, 36, 81,
+100, 144, 256 lanes); one-level chains; ragged images and shifted lattices on
+each axis.
 """
 import numpy as np
 import pytest
@@ -24,6 +25,7 @@ CHAINS = {
     "m2_12": [1, 2, 6, 12],
     "f2_12": [2, 6, 12],
     "p1_10": [1, 5, 10],
+    "f4_64": [4, 8, 16, 32, 64],
     "one_3": [3],
     "one_4": [4],
 }
