@@ -476,10 +476,17 @@ __device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs
         y[u][v] = yv;
         const int h = (sizeof(TX) == 4) ? ((u * V + v) & 1) : 0;
         if constexpr (sizeof(TX) == 4 && KAHAN) {
-          const TX t2 = __builtin_fmaf(yv, yv, -comp[h]);
-          const TX s2 = acc[h] + t2;
-          comp[h] = (s2 - acc[h]) - t2;
-          acc[h] = s2;
+          if (u * V + v < 2) {
+            // an accumulator's first term: the compensated step from (0, 0)
+            // gives acc = y^2 rounded and comp = 0 exactly (finite y), so
+            // take those values instead of computing y^2 - y^2
+            acc[h] = yv * yv;
+          } else {
+            const TX t2 = __builtin_fmaf(yv, yv, -comp[h]);
+            const TX s2 = acc[h] + t2;
+            comp[h] = (s2 - acc[h]) - t2;
+            acc[h] = s2;
+          }
         } else if constexpr (sizeof(TX) == 4) {
           acc[h] = __builtin_fmaf(yv, yv, acc[h]);
         } else {
