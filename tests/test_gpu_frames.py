@@ -132,11 +132,25 @@ def test_frames_full_size_sampled(ctx):
 
 def test_frames_reject_bad_arguments(ctx, smre):
     x = torch.zeros((2, 8, 8), dtype=torch.float32, device="cuda")
-    with pytest.raises(smre.SmreError):
-        ctx.incomplete_frames(x, 6, np.ones(7))
+    with pytest.raises(smre.SmreError):  # K = 7: blocks of 128 exceed every kernel
+        ctx.incomplete_frames(x, 7, np.ones(8))
     x[1, 3, 3] = float("nan")
     with pytest.raises(smre.SmreError):
         ctx.incomplete_frames(x, 2, bounds(2))
+
+
+def test_frames_k6_equal_single_calls(ctx):
+    """K = 6 frames run on the nested-hierarchy kernel: each frame bitwise
+    equal to the same image projected alone."""
+    K = 6
+    r2 = bounds(K)
+    frames = np.stack([gi.emitters(70, 81, n_e=6, seed=50 + f) for f in range(3)])
+    xs = torch.from_numpy(frames).to("cuda", dtype=torch.float32)
+    ctx.incomplete_frames(xs, K, r2, tol=1e-3, mode=1, max_inner=10000)
+    for f in range(3):
+        one = torch.from_numpy(frames[f]).to("cuda", dtype=torch.float32)
+        ctx.incomplete(one, K, r2, tol=1e-3, mode=1, max_inner=10000)
+        assert torch.equal(one, xs[f])
 
 
 # ---------------------------------------------------------------- phase families
