@@ -129,6 +129,7 @@ int timing_end(smre_ctx* c, TimingAcc& acc, hipStream_t s, int slot) {
 constexpr int kSigWords = 8;
 struct Plan {
   int R = 16;
+  int SI = 17;  // largest side of the sweep kernel instance (its LDS footprint)
   int nsides = 0;
   int sides[kMaxSides];
   double r2[kMaxSides];
@@ -145,12 +146,17 @@ struct Plan {
   size_t meta_rtab = 0, meta_bytes = 0;
 };
 
-// Footprint pitch of the sweep kernel instantiated for region side R (it
-// depends only on R and the largest side R + 1).
-int footprint_pitch(int R) {
+// Sweep kernel instances: region side R with largest side R + 1, and R = 16
+// with largest side 9 (a smaller LDS footprint, so more workgroups per CU,
+// for images whose sides are all at most 9).  The instance changes where a
+// region's pixels sit in LDS, not the arithmetic.
+int instance_smax(int R, int smax) { return (R == 16 && smax <= 9) ? 9 : R + 1; }
+
+// Footprint pitch of the instance (R, SI).
+int footprint_pitch(int R, int SI) {
   switch (R) {
     case 8: return PhaseShape<float, float, 8, 9>::P;
-    case 16: return PhaseShape<float, float, 16, 17>::P;
+    case 16: return SI == 9 ? PhaseShape<float, float, 16, 9>::P : PhaseShape<float, float, 16, 17>::P;
     case 32: return PhaseShape<float, float, 32, 33>::P;
     default: return 0;
   }
@@ -163,7 +169,7 @@ int footprint_pitch(int R) {
 // increment bytes.  Border classes: regions in the last row / column of
 // regions (class 2) and the one before (class 1) may hold fewer anchors.
 void build_round_tables(const Plan& pl, int64_t H, int64_t W, size_t es, RoundEntry* out) {
-  const int R = pl.R, P = footprint_pitch(R), TL = round_table_len(R);
+  const int R = pl.R, P = footprint_pitch(R, pl.SI), TL = round_table_len(R);
   for (int k = 0; k < pl.nsides; ++k) {
     const int S = pl.sides[k];
     const Pattern pt = pattern(R, S);
@@ -210,7 +216,7 @@ int choose_region(int smax, int requested) {
 }
 
 int plan_project(smre_dtype dt, int64_t H, int64_t W, const smre_params* p, Plan* pl,
-                 bool need_offsets) {
+                 bool need_offsets, int si_force = 0) {
   if (!p || !p->sides || !p->radius2) return SMRE_EINVAL;
   if (dt != SMRE_F32 && dt != SMRE_F64) return SMRE_EINVAL;
   if (H < 1 || W < 1 || H > (1 << 20) || W > (1 << 20)) return SMRE_EINVAL;
@@ -243,6 +249,11 @@ int plan_project(smre_dtype dt, int64_t H, int64_t W, const smre_params* p, Plan
   pl->R = choose_region(pl->smax, p->region);
   if (pl->R != 8 && pl->R != 16 && pl->R != 32) return SMRE_EINVAL;
   if (pl->R < pl->smax - 1) return SMRE_EINVAL;
+  // kernel instance: the caller's (a batch or server shares one), else the
+  // smallest that holds the sides
+  pl->SI = si_force ? si_force : instance_smax(pl->R, pl->smax);
+  if (pl->SI < pl->smax || (pl->SI != pl->R + 1 && !(pl->R == 16 && pl->SI == 9)))
+    return SMRE_EINVAL;
   pl->nry = (int)((H + pl->R - 1) / pl->R);
   pl->nrx = (int)((W + pl->R - 1) / pl->R);
   const size_t es = (p->inc == SMRE_INC_BF16) ? 2 : (dt == SMRE_F64 ? 8 : 4);
@@ -363,33 +374,35 @@ struct PhaseLaunch {
   unsigned char* q;
 };
 
-template <typename TX, typename TQ, int R, bool KAHAN>
+template <typename TX, typename TQ, int R, int SMAX, bool KAHAN>
 void launch_phase(const ImageDesc& a, const PhaseLaunch& l, hipStream_t s) {
-  constexpr int SMAX = R + 1;
   hipLaunchKernelGGL((region_phase<TX, TQ, R, SMAX, KAHAN>), dim3(l.blocks), dim3(128), 0, s, a,
                      l.cy, l.cx, l.ncx, l.done, l.abort, l.q);
 }
 
 template <typename TX, typename TQ, bool KAHAN>
-int launch_phase_r(int R, const ImageDesc& a, const PhaseLaunch& l, hipStream_t s) {
+int launch_phase_r(int R, int SI, const ImageDesc& a, const PhaseLaunch& l, hipStream_t s) {
   switch (R) {
-    case 8: launch_phase<TX, TQ, 8, KAHAN>(a, l, s); break;
-    case 16: launch_phase<TX, TQ, 16, KAHAN>(a, l, s); break;
-    case 32: launch_phase<TX, TQ, 32, KAHAN>(a, l, s); break;
+    case 8: launch_phase<TX, TQ, 8, 9, KAHAN>(a, l, s); break;
+    case 16:
+      if (SI == 9) launch_phase<TX, TQ, 16, 9, KAHAN>(a, l, s);
+      else launch_phase<TX, TQ, 16, 17, KAHAN>(a, l, s);
+      break;
+    case 32: launch_phase<TX, TQ, 32, 33, KAHAN>(a, l, s); break;
     default: return SMRE_EINVAL;
   }
   HIP_OK(hipGetLastError());
   return SMRE_OK;
 }
 
-int launch_phase_any(smre_dtype dt, int inc, int kahan, int R, const ImageDesc& a,
+int launch_phase_any(smre_dtype dt, int inc, int kahan, int R, int SI, const ImageDesc& a,
                      const PhaseLaunch& l, hipStream_t s) {
-  if (dt == SMRE_F64) return launch_phase_r<double, double, false>(R, a, l, s);
+  if (dt == SMRE_F64) return launch_phase_r<double, double, false>(R, SI, a, l, s);
   if (inc == SMRE_INC_BF16)
-    return kahan ? launch_phase_r<float, bf16_t, true>(R, a, l, s)
-                 : launch_phase_r<float, bf16_t, false>(R, a, l, s);
-  return kahan ? launch_phase_r<float, float, true>(R, a, l, s)
-               : launch_phase_r<float, float, false>(R, a, l, s);
+    return kahan ? launch_phase_r<float, bf16_t, true>(R, SI, a, l, s)
+                 : launch_phase_r<float, bf16_t, false>(R, SI, a, l, s);
+  return kahan ? launch_phase_r<float, float, true>(R, SI, a, l, s)
+               : launch_phase_r<float, float, false>(R, SI, a, l, s);
 }
 
 template <typename TX>
@@ -520,7 +533,7 @@ int project_impl(smre_ctx* c, smre_dtype dt, void* x, int64_t H, int64_t W, int6
       int slot;
       rc = timing_begin(c, tacc, s, &slot);
       if (rc) return rc;
-      rc = launch_phase_any(dt, p->inc, p->kahan, pl.R, a, l, s);
+      rc = launch_phase_any(dt, p->inc, p->kahan, pl.R, pl.SI, a, l, s);
       if (rc) return rc;
       rc = timing_end(c, tacc, s, slot);
       if (rc) return rc;
@@ -1194,6 +1207,7 @@ int nested_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t 
 // ---------------------------------------------------------------- batches
 struct BatchPlan {
   int R = 16;
+  int SI = 17;  // kernel instance shared by every image (instance_smax of the batch)
   int n = 0;
   std::vector<Plan> plans;
   std::vector<size_t> qoff;       // byte offset of each image's increments
@@ -1209,6 +1223,11 @@ int plan_batch(smre_dtype dt, int n, const smre_batch_image* im, const smre_batc
                int R, BatchPlan* B, bool need_offsets) {
   B->R = R;
   B->n = n;
+  int smax_all = 1;
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < im[i].n_sides && im[i].sides; ++k)
+      smax_all = std::max(smax_all, (int)im[i].sides[k]);
+  B->SI = instance_smax(R, smax_all);
   B->plans.assign(n, Plan());
   B->qoff.assign(n, 0);
   B->roff_off.assign(n, 0);
@@ -1230,7 +1249,7 @@ int plan_batch(smre_dtype dt, int n, const smre_batch_image* im, const smre_batc
     p.kahan = bp->kahan;
     p.guard_rel = bp->guard_rel;
     if (!im[i].x || im[i].ld < im[i].W) return SMRE_EINVAL;
-    int rc = plan_project(dt, im[i].H, im[i].W, &p, &B->plans[i], need_offsets);
+    int rc = plan_project(dt, im[i].H, im[i].W, &p, &B->plans[i], need_offsets, B->SI);
     if (rc) return rc;
     B->qoff[i] = B->qbytes;
     B->qbytes += align_up(B->plans[i].qbytes, kPage);
@@ -1253,16 +1272,16 @@ int plan_batch(smre_dtype dt, int n, const smre_batch_image* im, const smre_batc
   return SMRE_OK;
 }
 
-template <typename TX, typename TQ, int R, bool KAHAN>
+template <typename TX, typename TQ, int R, int SMAX, bool KAHAN>
 int batch_grid(int cus, int want) {
   int occ = 0;
   HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &occ, (const void*)region_phase_batch<TX, TQ, R, R + 1, KAHAN>, 128, 0));
+      &occ, (const void*)region_phase_batch<TX, TQ, R, SMAX, KAHAN>, 128, 0));
   return std::max(1, std::min(want, std::max(1, occ) * cus));
 }
 
 template <typename TX, typename TQ, bool KAHAN>
-int launch_batch_phase(int R, int grid, const ImageDesc* d, BatchCtl* ctl,
+int launch_batch_phase(int R, int SI, int grid, const ImageDesc* d, BatchCtl* ctl,
                        const WorkItem* items, const int* cnt, unsigned char* q, hipStream_t s) {
   switch (R) {
     case 8:
@@ -1270,8 +1289,12 @@ int launch_batch_phase(int R, int grid, const ImageDesc* d, BatchCtl* ctl,
                          ctl, items, cnt, q);
       break;
     case 16:
-      hipLaunchKernelGGL((region_phase_batch<TX, TQ, 16, 17, KAHAN>), dim3(grid), dim3(128), 0, s,
-                         d, ctl, items, cnt, q);
+      if (SI == 9)
+        hipLaunchKernelGGL((region_phase_batch<TX, TQ, 16, 9, KAHAN>), dim3(grid), dim3(128), 0,
+                           s, d, ctl, items, cnt, q);
+      else
+        hipLaunchKernelGGL((region_phase_batch<TX, TQ, 16, 17, KAHAN>), dim3(grid), dim3(128), 0,
+                           s, d, ctl, items, cnt, q);
       break;
     case 32:
       hipLaunchKernelGGL((region_phase_batch<TX, TQ, 32, 33, KAHAN>), dim3(grid), dim3(128), 0, s,
@@ -1284,11 +1307,13 @@ int launch_batch_phase(int R, int grid, const ImageDesc* d, BatchCtl* ctl,
 }
 
 template <typename TX, typename TQ, bool KAHAN>
-int grid_for_batch(smre_ctx* c, int R, int want) {
+int grid_for_batch(smre_ctx* c, int R, int SI, int want) {
   switch (R) {
-    case 8: return batch_grid<TX, TQ, 8, KAHAN>(c->cus, want);
-    case 16: return batch_grid<TX, TQ, 16, KAHAN>(c->cus, want);
-    default: return batch_grid<TX, TQ, 32, KAHAN>(c->cus, want);
+    case 8: return batch_grid<TX, TQ, 8, 9, KAHAN>(c->cus, want);
+    case 16:
+      return SI == 9 ? batch_grid<TX, TQ, 16, 9, KAHAN>(c->cus, want)
+                     : batch_grid<TX, TQ, 16, 17, KAHAN>(c->cus, want);
+    default: return batch_grid<TX, TQ, 32, 33, KAHAN>(c->cus, want);
   }
 }
 
@@ -1306,8 +1331,8 @@ struct BatchDev {
 };
 
 template <typename TX>
-int enqueue_batch_sweep(smre_dtype dt, const smre_batch_params* bp, int R, const BatchDev& D,
-                        bool check, hipStream_t s) {
+int enqueue_batch_sweep(smre_dtype dt, const smre_batch_params* bp, int R, int SI,
+                        const BatchDev& D, bool check, hipStream_t s) {
   (void)dt;
   const dim3 cg(std::max(1, std::min(64, D.maxh)), D.n);
   if (check)
@@ -1315,17 +1340,17 @@ int enqueue_batch_sweep(smre_dtype dt, const smre_batch_params* bp, int R, const
   for (int color = 0; color < 4; ++color) {
     int rc;
     if (sizeof(TX) == 8)
-      rc = launch_batch_phase<double, double, false>(R, D.grid[color], D.desc, D.ctl,
+      rc = launch_batch_phase<double, double, false>(R, SI, D.grid[color], D.desc, D.ctl,
                                                      D.items[color], D.cnt + color, D.q, s);
     else if (bp->inc == SMRE_INC_BF16)
-      rc = bp->kahan ? launch_batch_phase<float, bf16_t, true>(R, D.grid[color], D.desc, D.ctl,
+      rc = bp->kahan ? launch_batch_phase<float, bf16_t, true>(R, SI, D.grid[color], D.desc, D.ctl,
                                                                 D.items[color], D.cnt + color, D.q, s)
-                     : launch_batch_phase<float, bf16_t, false>(R, D.grid[color], D.desc, D.ctl,
+                     : launch_batch_phase<float, bf16_t, false>(R, SI, D.grid[color], D.desc, D.ctl,
                                                                  D.items[color], D.cnt + color, D.q, s);
     else
-      rc = bp->kahan ? launch_batch_phase<float, float, true>(R, D.grid[color], D.desc, D.ctl,
+      rc = bp->kahan ? launch_batch_phase<float, float, true>(R, SI, D.grid[color], D.desc, D.ctl,
                                                                D.items[color], D.cnt + color, D.q, s)
-                     : launch_batch_phase<float, float, false>(R, D.grid[color], D.desc, D.ctl,
+                     : launch_batch_phase<float, float, false>(R, SI, D.grid[color], D.desc, D.ctl,
                                                                 D.items[color], D.cnt + color, D.q, s);
     if (rc) return rc;
   }
@@ -1415,9 +1440,10 @@ int batch_setup(smre_ctx* c, smre_dtype dt, int n, const smre_batch_image* im,
   D->n = n;
   for (int c2 = 0; c2 < 4; ++c2) {
     int g;
-    if (sizeof(TX) == 8) g = grid_for_batch<double, double, false>(c, B.R, B.nitems[c2]);
-    else if (bp->inc == SMRE_INC_BF16) g = grid_for_batch<float, bf16_t, true>(c, B.R, B.nitems[c2]);
-    else g = grid_for_batch<float, float, true>(c, B.R, B.nitems[c2]);
+    if (sizeof(TX) == 8) g = grid_for_batch<double, double, false>(c, B.R, B.SI, B.nitems[c2]);
+    else if (bp->inc == SMRE_INC_BF16)
+      g = grid_for_batch<float, bf16_t, true>(c, B.R, B.SI, B.nitems[c2]);
+    else g = grid_for_batch<float, float, true>(c, B.R, B.SI, B.nitems[c2]);
     if (bp->grid > 0) g = std::min(bp->grid, std::max(1, B.nitems[c2]));
     D->grid[c2] = std::max(1, g);
   }
@@ -1517,7 +1543,7 @@ int batch_impl(smre_ctx* c, smre_dtype dt, int n, const smre_batch_image* im,
       hipEvent_t e0 = c->ev[0], e1 = c->ev[1];
       HIP_OK(hipEventRecord(e0, s));
       for (int k = 0; k < 2; ++k) {
-        rc = enqueue_batch_sweep<TX>(dt, bp, Rc, D, false, s);
+        rc = enqueue_batch_sweep<TX>(dt, bp, Rc, B.SI, D, false, s);
         if (rc) return rc;
       }
       HIP_OK(hipEventRecord(e1, s));
@@ -1549,7 +1575,7 @@ int batch_impl(smre_ctx* c, smre_dtype dt, int n, const smre_batch_image* im,
     HIP_OK(hipStreamSynchronize(s));
     for (int g = 0; g < 2; ++g) {
       HIP_OK(hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
-      int rc2 = enqueue_batch_sweep<TX>(dt, bp, R, D, g == 1, c->capture);
+      int rc2 = enqueue_batch_sweep<TX>(dt, bp, R, B.SI, D, g == 1, c->capture);
       hipGraph_t graph = nullptr;
       HIP_OK(hipStreamEndCapture(c->capture, &graph));
       if (rc2) return rc2;
@@ -1569,7 +1595,7 @@ int batch_impl(smre_ctx* c, smre_dtype dt, int n, const smre_batch_image* im,
     if (bp->use_graph) {
       HIP_OK(hipGraphLaunch(gx[check ? 1 : 0], s));
     } else {
-      rc = enqueue_batch_sweep<TX>(dt, bp, R, D, check, s);
+      rc = enqueue_batch_sweep<TX>(dt, bp, R, B.SI, D, check, s);
       if (rc) return rc;
     }
     rc = timing_end(c, tacc, s, slot);
@@ -1764,7 +1790,7 @@ class HipBackend : public smre_serve::Backend {
     bp.check_every = 1;
     bp.guard_rel = cfg_.guard_rel;
     HIP_OK(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
-    const int rc = enqueue_batch_sweep<float>(SMRE_F32, &bp, 16, D, true, stream_);
+    const int rc = enqueue_batch_sweep<float>(SMRE_F32, &bp, 16, 17, D, true, stream_);
     HIP_OK(hipStreamEndCapture(stream_, &graph_));
     if (rc) return rc;
     HIP_OK(hipGraphInstantiate(&gx_, graph_, nullptr, nullptr, 0));
@@ -1777,7 +1803,7 @@ class HipBackend : public smre_serve::Backend {
   size_t footprint(const smre_serve::Request& r) const override {
     Plan pl;
     smre_params p = params_of(r);
-    if (plan_project(SMRE_F32, r.H, r.W, &p, &pl, false)) return 0;
+    if (plan_project(SMRE_F32, r.H, r.W, &p, &pl, false, 17)) return 0;
     return layout(pl, r, nullptr);
   }
 
@@ -1785,7 +1811,7 @@ class HipBackend : public smre_serve::Backend {
     Slot& sl = slot_[s];
     smre_params p = params_of(r);
     sl.plan = Plan();
-    int rc = plan_project(SMRE_F32, r.H, r.W, &p, &sl.plan, true);
+    int rc = plan_project(SMRE_F32, r.H, r.W, &p, &sl.plan, true, 17);
     if (rc) return rc;
     size_t off_roff, off_x, off_prev;
     size_t offs[3];

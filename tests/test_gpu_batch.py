@@ -76,6 +76,24 @@ def test_batch_equals_single_bitwise(ctx, dt):
         assert torch.equal(x, y)
 
 
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+def test_kernel_instance_does_not_change_bits(ctx, dt):
+    """Sides up to 9 at R = 16 run on the instance with the smaller LDS
+    footprint alone, but on the side-17 instance in a batch that also holds a
+    side-12 image: only the pixels' LDS placement differs, so the bits and the
+    stopping sweep must not."""
+    x0s = images(np.float32)[:3]
+    small = list(range(1, 10))
+    sides_l = [small, small, [1, 2, 5, 12]]
+    r2_l = [oracle.chi2_bounds(s) for s in sides_l]
+    xs = [dev(x, dt) for x in x0s]
+    ctx.project_batch(xs, sides_l, r2_l, tol=1e-5, max_sweeps=3000, region=16)
+    for x0, x, s, r in zip(x0s[:2], xs[:2], sides_l[:2], r2_l[:2]):
+        y = dev(x0, dt)
+        ctx.project(y, s, r, tol=1e-5, max_sweeps=3000, region=16)
+        assert torch.equal(x, y)
+
+
 def test_batch_per_image_sides(ctx):
     x0s = images()
     sides_l = [[1, 2, 3], list(range(1, 9)), [2, 5], [1, 4, 7, 9], [1]]
