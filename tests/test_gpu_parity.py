@@ -218,6 +218,42 @@ def test_strided_rows(ctx):
     assert torch.all(big[:, W:] == 7.0)
 
 
+@pytest.mark.parametrize("H,W,sides", [(1, 1, [1]), (1, 50, [1]), (50, 1, [1]),
+                                       (2, 70, [1, 2]), (70, 3, [1, 2, 3])])
+def test_degenerate_shapes_match_oracle(ctx, H, W, sides):
+    """One-pixel, one-row and one-column images (the window families shrink
+    to what fits), per sweep in region order."""
+    x0 = gi.gaussian(H, W, seed=H + 3 * W, scale=3.0)
+    r2 = oracle.chi2_bounds(sides)
+    for R in (8, 16):
+        ref, _, _ = oracle.dykstra(x0, sides, r2, tol=0, max_sweeps=3, order=oracle.ORDER_REGION,
+                                   region=R)
+        z, _, rep = gpu_project(ctx, x0, sides, r2, tol=0, max_sweeps=3, region=R)
+        assert rep["sweeps"] == 3
+        assert relerr(z, ref) <= 1e-13
+
+
+def test_degenerate_shapes_icd(ctx):
+    """ICD on images smaller than a block: blocks are clipped, and squares
+    that do not fit are skipped."""
+    for H, W, K in ((1, 1, 2), (1, 40, 3), (40, 1, 3), (5, 7, 4)):
+        x0 = gi.gaussian(H, W, seed=H * W + K, scale=3.0)
+        r2 = oracle.chi2_bounds([1 << k for k in range(K + 1)])
+        ref, _ = oracle.icd(x0, K, r2, tol=1e-13, mode=oracle.TOL_MAXABS, max_inner=100000)
+        x = dev(x0)
+        ctx.incomplete(x, K, r2, tol=1e-13, mode=0, max_inner=100000)
+        assert relerr(x.cpu().numpy(), ref) <= 1e-12
+
+
+def test_empty_image_rejected(ctx, smre):
+    for shape in ((0, 16), (16, 0)):
+        x = torch.zeros(shape, dtype=torch.float64, device="cuda")
+        with pytest.raises(smre.SmreError):
+            ctx.project(x, [1], oracle.chi2_bounds([1]), tol=1e-6)
+        with pytest.raises(smre.SmreError):
+            ctx.incomplete(x, 0, oracle.chi2_bounds([1]))
+
+
 def test_nonfinite_rejected(ctx, smre):
     x = dev(np.ones((16, 16)))
     x[3, 4] = float("nan")
