@@ -84,8 +84,8 @@ def workload(name):
 
 
 def host_cores():
-    """Host threads this process may use (the GPU machine grants a share of its
-    cores to each GPU: at most 16 are used)."""
+    """Host threads this process may use: its affinity mask, at most 16 (a
+    node's host cores are shared among its GPUs)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
