@@ -212,7 +212,13 @@ def bench_batch(args):
            "config": {"workload": "batch64_uneven_128-768_sides1-8_fp32", "images": len(x0s),
                       "tol": 1e-5, "region": reps[-1][0]["region"]},
            "sweeps_min_max": [min(sweeps), max(sweeps)],
-           "achieved_GBps_alg": by / el / 1e9, "sweep_graph_ms_total": kms}
+           "achieved_GBps_alg": by / el / 1e9, "sweep_graph_ms_total": kms,
+           # the whole batch's algorithmic bytes (each image's increments and
+           # pixels, read and written once per sweep it runs) over its wall
+           # time, tail included
+           "roofline": {"bound": "hbm", "achieved": by / el / 1e9, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": by / el / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                        "kernel": "region_phase_batch"}}
     print(json.dumps(out), flush=True)
 
 
