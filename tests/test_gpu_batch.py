@@ -94,6 +94,24 @@ def test_kernel_instance_does_not_change_bits(ctx, dt):
         assert torch.equal(x, y)
 
 
+@pytest.mark.parametrize("sides_l", [[list(range(1, 9))] * 3,
+                                     [list(range(1, 9)), [1, 3, 9], [1, 2, 5, 12]]])
+def test_batch_bf16_equals_single_bitwise(ctx, smre, sides_l):
+    """BF16-stored increments: each image in the batch gets the bits and the
+    stopping sweep it gets alone (both kernel instances: largest side 8, and
+    12 in the mix)."""
+    x0s = images(np.float32)[:3]
+    r2_l = [oracle.chi2_bounds(s) for s in sides_l]
+    xs = [dev(x, torch.float32) for x in x0s]
+    rc, reps = ctx.project_batch(xs, sides_l, r2_l, tol=1e-5, max_sweeps=3000, region=16,
+                                 inc=smre.INC_BF16)
+    for x0, x, rep, s, r in zip(x0s, xs, reps, sides_l, r2_l):
+        y = dev(x0, torch.float32)
+        _, rep1 = ctx.project(y, s, r, tol=1e-5, max_sweeps=3000, region=16, inc=smre.INC_BF16)
+        assert rep["sweeps"] == rep1["sweeps"]
+        assert torch.equal(x, y)
+
+
 def test_batch_per_image_sides(ctx):
     x0s = images()
     sides_l = [[1, 2, 3], list(range(1, 9)), [2, 5], [1, 4, 7, 9], [1]]

@@ -73,6 +73,28 @@ def test_alone_and_in_mix_identical(smre):
         assert lat > 0
 
 
+def test_bf16_increments_alone_and_served_identical(smre):
+    """A server storing increments in BF16 gives each request the bits of the
+    same image solved alone with BF16 increments at R = 16."""
+    reqs = []
+    for k, (H, W) in enumerate([(64, 72), (90, 64), (50, 100)]):
+        x0 = gi.emitters(H, W, n_e=max(2, H * W // 300), seed=20 + k).astype(np.float32)
+        sides = list(range(1, 9)) if k != 1 else [1, 2, 4, 12]
+        reqs.append((x0, sides, oracle.chi2_bounds(sides)))
+    srv = smre.Server(max_active=3, inc=smre.INC_BF16)
+    tickets = [srv.submit(x0, s, r2, tol=1e-5, max_sweeps=3000) for x0, s, r2 in reqs]
+    outs = [wait(srv, t, r[0].shape) for t, r in zip(tickets, reqs)]
+    srv.close()
+    ctx = smre.Context(0)
+    for (x0, sides, r2), (rc, z, rep, lat) in zip(reqs, outs):
+        x = torch.from_numpy(x0).cuda()
+        _, rep1 = ctx.project(x, sides, r2, tol=1e-5, max_sweeps=3000, region=16,
+                              inc=smre.INC_BF16)
+        assert rep["sweeps"] == rep1["sweeps"]
+        assert np.array_equal(z, x.cpu().numpy())
+    ctx.close()
+
+
 def test_matches_oracle_per_sweep(smre):
     x0 = gi.emitters(80, 72, n_e=20, seed=3).astype(np.float32)
     sides = list(range(1, 9))
