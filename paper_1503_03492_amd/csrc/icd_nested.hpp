@@ -215,7 +215,8 @@ void icd_nested_phase(NestedArgs a) {
       if constexpr (MEANABS) tot += u;
       else tot = tot > u ? tot : u;
     }
-    if (MEANABS ? (tot <= (T)a.tol * npix) : (tot < (T)a.tol)) {
+    // the sum in the image precision, the comparison in FP64 (as icd_phase)
+    if (MEANABS ? ((double)tot <= a.tol * (double)npix) : ((double)tot < a.tol)) {
       met = true;
       break;
     }
