@@ -497,6 +497,11 @@ __device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs
     if constexpr (sizeof(TX) == 4 && KAHAN) lane_sum = (acc[0] - comp[0]) + (acc[1] - comp[1]);
     else if constexpr (sizeof(TX) == 4) lane_sum = acc[0] + acc[1];
     else lane_sum = acc[0];
+    // the next round's byte end into a scalar register here, mid-round, so
+    // the vector-to-scalar hand-off is long done when the loop test and the
+    // next round's page check use it
+    uint32_t rb_end_n = __builtin_amdgcn_readfirstlane(en.y);
+    __asm__ volatile("" : "+s"(rb_end_n));
     const TX n = group_sum<G>(lane_sum);
 
     // 3) x' = t y into the footprint, I' = y - x' into the ring (pixels
@@ -565,7 +570,7 @@ __device__ __forceinline__ void run_side(const ImageDesc& a, Consumer& c, TX* xs
     lds_store(c.consumed, (int)((qb0 + rb_end) / kPage));
     rb = rb_end;
     e = en;
-    rb_end = __builtin_amdgcn_readfirstlane(en.y);  // read a round ago, long arrived
+    rb_end = rb_end_n;
   } while (++i < nrounds);
   c.qb = qb0 + rb;
 }
