@@ -185,14 +185,14 @@ int smre_dykstra_incomplete(smre_ctx* ctx, smre_dtype dtype, void* x, int64_t H,
  * allocation): same arguments, same results and report (except kernel_ms and
  * kernel_launches, which are 0: no per-kernel timing), but no hipMalloc,
  * hipFree or other allocating call on any path.  Its device scratch (the work
- * counters, their sums and the feasibility report's per-level maxima) is a
- * fixed 32,960-byte static array per GPU, located when the context is created;
+ * counters of the blocks) is a fixed 32,768-byte static array per GPU, located
+ * when the context is created;
  * it does not grow with the image, so the only size limit is K <= 5
  * (SMRE_EINVAL beyond, as for smre_dykstra_incomplete).  Every call on one
  * GPU uses that GPU's single copy and overwrites it: calls that overlap on one
  * GPU (other host threads, other streams) race and must be serialised by the
- * caller.  The context still holds the control block and events used by the
- * input check and the report, allocated by smre_ctx_create. */
+ * caller.  The context still holds the control block (input check, counter
+ * sums, feasibility report) and the events, allocated by smre_ctx_create. */
 int smre_dykstra_incomplete_noalloc(smre_ctx* ctx, smre_dtype dtype, void* x, int64_t H,
                                     int64_t W, int64_t ld, int32_t K, const double* radius2,
                                     double tol, int32_t tolmode, int32_t max_inner,
@@ -346,7 +346,8 @@ int smre_serve_poll(smre_server* s, uint64_t ticket, float* out_host, size_t out
 int smre_serve_stats(smre_server* s, smre_serve_counters* out);
 
 /* FP64 feasibility of x (device): *out = max_S sum_S x^2 / r2_S - 1 over all
- * windows of the given sides (<= 0 means every constraint holds). */
+ * windows of the given sides (1 <= side <= min(H, W), side <= 96; <= 0 means
+ * every constraint holds). */
 int smre_max_violation(smre_ctx* ctx, smre_dtype dtype, const void* x, int64_t H, int64_t W,
                        int64_t ld, int32_t n_sides, const int32_t* sides, const double* radius2,
                        void* stream, double* out);

@@ -36,6 +36,7 @@ struct Ctrl {
   unsigned long long delta_key;  // running max |x - prev| of the checked sweep
   double last_delta;
   unsigned long long viol_key;   // running max violation
+  unsigned long long icd_sum[4]; // an ICD call's summed work counters
 };
 
 template <typename TX>
@@ -99,16 +100,84 @@ __global__ __launch_bounds__(256) void nonfinite_kernel(const TX* x, int64_t ld,
   if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&ctrl->nonfinite, 1);
 }
 
-// Feasibility: max over windows of side s of sum x^2 / r2 - 1, in FP64.  A
-// block takes a tile of VT x VW window anchors: it stages the squares of the
-// (VT + s - 1) x (VW + s - 1) pixels in LDS, sums each row over s columns,
-// then those row sums over s rows (O(s) adds per window instead of s^2 loads).
-// blockIdx.z selects a frame of a movie (frames fstride elements apart).
-// Tiles of 32 x 64 anchors for sides up to 33, 16 x 32 up to 65.
-constexpr int kViolTileH = 32, kViolTileW = 64, kViolMaxSide = 33;
-constexpr int kViolTileH2 = 16, kViolTileW2 = 32, kViolMaxSide2 = 65;
-template <typename TX, int kViolTileH = smre::kViolTileH, int kViolTileW = smre::kViolTileW,
-          int kViolMaxSide = smre::kViolMaxSide>
+// Feasibility: max over windows S of the requested sides of sum_S x^2 / r2_s - 1,
+// in FP64, folded into ctrl->viol_key; blockIdx.z selects a frame of a movie
+// (frames fstride elements apart).
+//
+// All sides up to SMAX in one pass.  A workgroup owns 4 RPL x 64 window anchors
+// and stages the squares of their (4 RPL + SMAX - 1) x (64 + SMAX - 1) pixels
+// in LDS.  Lane (c, g) owns anchor column c and rows RPL g .. RPL g + RPL - 1:
+// it keeps h[k] = sum_{l < s} x^2[RPL g + k][c + l] for the rows its windows
+// touch and grows it by one column as the side goes 1, 2, ...; a window's sum
+// is then its s row sums added top to bottom.  Those are the row-then-column
+// sums of violation_kernel in the same order, so both give the same bits.  The
+// largest ratio of a side comes from its largest sum (x -> x / r2 - 1 does not
+// decrease under rounding either).
+constexpr int kFeasMaxSide = 32;
+constexpr int feas_rows_per_lane(int smax) { return smax <= 16 ? 16 : 8; }
+constexpr int feas_tile_rows(int smax) { return 4 * feas_rows_per_lane(smax); }
+struct FeasSides {
+  double r2[kFeasMaxSide + 1];  // r2[s] > 0: side s requested with that bound; 0: not
+  int32_t smax;                 // largest requested side
+};
+
+template <typename TX, int SMAX>
+__global__ __launch_bounds__(256) void feasibility_kernel(const TX* __restrict__ x,
+                                                          int64_t fstride, int64_t ld, int H,
+                                                          int W, FeasSides fs, Ctrl* ctrl) {
+  constexpr int RPL = feas_rows_per_lane(SMAX);
+  constexpr int ER = 4 * RPL + SMAX - 1, EC = 64 + SMAX - 1;
+  constexpr int ROWS = RPL + SMAX - 1;  // rows one lane's windows touch
+  __shared__ double sq[ER][EC];
+  x += (int64_t)blockIdx.z * fstride;
+  const int a0 = blockIdx.y * (4 * RPL), b0 = blockIdx.x * 64;
+  for (int i = threadIdx.x; i < ER * EC; i += 256) {
+    const int r = i / EC, cc = i - (i / EC) * EC;
+    double v = 0.0;
+    if (a0 + r < H && b0 + cc < W) {
+      v = (double)x[(int64_t)(a0 + r) * ld + b0 + cc];
+      v = v * v;
+    }
+    sq[r][cc] = v;
+  }
+  __syncthreads();
+  const int c = threadIdx.x & 63, r0 = (threadIdx.x >> 6) * RPL;
+  double h[ROWS];
+#pragma unroll
+  for (int k = 0; k < ROWS; ++k) h[k] = 0.0;
+  double worst = -1.0;
+#pragma unroll
+  for (int s = 1; s <= SMAX; ++s) {
+    // s is a compile-time constant here, so every h[] index is static
+    if (s <= fs.smax) {
+#pragma unroll
+      for (int k = 0; k < ROWS; ++k) h[k] += sq[r0 + k][c + s - 1];
+      const int nrow = min(RPL, H - s + 1 - a0 - r0);  // anchor rows inside the image
+      if (fs.r2[s] > 0.0 && b0 + c <= W - s && nrow > 0) {
+        double m = 0.0;
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+          if (j < nrow) {
+            double n = 0.0;
+#pragma unroll
+            for (int k = 0; k < s; ++k) n += h[j + k];
+            m = fmax(m, n);
+          }
+        }
+        worst = fmax(worst, m / fs.r2[s] - 1.0);
+      }
+    }
+  }
+  worst = block_max<TX>(worst);
+  if (threadIdx.x == 0) key_max(&ctrl->viol_key, dkey(worst));
+}
+
+// Sides above kFeasMaxSide, one launch per side: a block takes 16 x 32 window
+// anchors, stages the squares of the (16 + s - 1) x (32 + s - 1) pixels in LDS,
+// sums each row over s columns, then those row sums over s rows (O(s) adds
+// per window instead of s^2 loads).
+constexpr int kViolTileH = 16, kViolTileW = 32, kViolMaxSide = 96;
+template <typename TX>
 __global__ __launch_bounds__(256) void violation_kernel(const TX* x, int64_t fstride, int64_t ld,
                                                         int H, int W, int s, double r2,
                                                         Ctrl* ctrl) {

@@ -82,6 +82,9 @@ struct IcdArgs {
   // and (square, pixel) updates to words 0, 1, 2 of slot (block id mod
   // kIcdSlots), so no line takes more than a share of the blocks' atomics.
   unsigned long long* counters;
+  // null, or a flag that the input check before the call raises for a
+  // non-finite input: every block then leaves the image as it is
+  const int* skip;
   // q = n / d for the launch's gridDim.x and gridDim.x * gridDim.y by a
   // multiply-high and shifts (udiv_magic), so the uniform block-index split
   // costs no VALU division sequence
@@ -344,6 +347,7 @@ __device__ __forceinline__ void icd_block(const IcdArgs& a, unsigned tx, unsigne
 // neighbours (icd_remap).  A wave adds its counts to one counter slot.
 template <typename T, int K, bool MEANABS>
 __global__ __launch_bounds__(64) void icd_phase(IcdArgs a) {
+  if (a.skip && *a.skip) return;
   IcdCount cnt;
   const unsigned w = blockIdx.x;
   if (a.run == 1) {

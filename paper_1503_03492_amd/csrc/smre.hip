@@ -405,43 +405,85 @@ int launch_phase_any(smre_dtype dt, int inc, int kahan, int R, int SI, const Ima
                : launch_phase_r<float, float, false>(R, SI, a, l, s);
 }
 
+// Feasibility of frames stacked fstride elements apart over the sides (each
+// at most kViolMaxSide; sides longer than the image have no window and are
+// skipped), folded into ctrl->viol_key as enqueued work on s: sides up to
+// kFeasMaxSide in one pass per launch of up to 65535 frames, longer ones one
+// launch each.  The caller resets viol_key and reads it back.
+template <typename TX>
+int enqueue_feasibility(const void* x, int64_t H, int64_t W, int64_t ld, int64_t fstride,
+                        int64_t frames, int n, const int* sides, const double* r2, Ctrl* ctrl,
+                        hipStream_t s) {
+  FeasSides fs;
+  std::memset(&fs, 0, sizeof fs);
+  int smin = 0;
+  std::vector<int> longer;
+  for (int k = 0; k < n; ++k) {
+    const int sk = sides[k];
+    if (sk < 1 || sk > kViolMaxSide) return SMRE_EINVAL;
+    if (sk > H || sk > W) continue;
+    if (sk > kFeasMaxSide) {
+      longer.push_back(k);
+      continue;
+    }
+    // a side listed twice keeps its smaller bound (the larger violation)
+    fs.r2[sk] = fs.r2[sk] > 0.0 ? std::min(fs.r2[sk], r2[k]) : r2[k];
+    fs.smax = std::max(fs.smax, sk);
+    smin = smin ? std::min(smin, sk) : sk;
+  }
+  for (int64_t f0 = 0; f0 < frames; f0 += 65535) {
+    const unsigned nz = (unsigned)std::min<int64_t>(65535, frames - f0);
+    const TX* xf = (const TX*)x + f0 * fstride;
+    if (fs.smax > 0) {
+      const int tr = feas_tile_rows(fs.smax <= 16 ? 16 : 32);
+      const dim3 grid((unsigned)((W - smin + 64) / 64), (unsigned)((H - smin + tr) / tr), nz);
+      if (fs.smax <= 8)
+        hipLaunchKernelGGL((feasibility_kernel<TX, 8>), grid, dim3(256), 0, s, xf, fstride, ld,
+                           (int)H, (int)W, fs, ctrl);
+      else if (fs.smax <= 16)
+        hipLaunchKernelGGL((feasibility_kernel<TX, 16>), grid, dim3(256), 0, s, xf, fstride, ld,
+                           (int)H, (int)W, fs, ctrl);
+      else
+        hipLaunchKernelGGL((feasibility_kernel<TX, 32>), grid, dim3(256), 0, s, xf, fstride, ld,
+                           (int)H, (int)W, fs, ctrl);
+    }
+    for (int k : longer) {
+      const dim3 grid((unsigned)((W - sides[k] + kViolTileW) / kViolTileW),
+                      (unsigned)((H - sides[k] + kViolTileH) / kViolTileH), nz);
+      hipLaunchKernelGGL((violation_kernel<TX>), grid, dim3(256), 0, s, xf, fstride, ld, (int)H,
+                         (int)W, sides[k], r2[k], ctrl);
+    }
+  }
+  HIP_OK(hipGetLastError());
+  return SMRE_OK;
+}
+
 template <typename TX>
 int run_violation(smre_ctx* c, const void* x, int64_t H, int64_t W, int64_t ld, int n,
                   const int* sides, const double* r2, hipStream_t s, double* out,
                   int64_t frames = 1) {
-  for (int64_t f0 = 0; f0 < frames; f0 += 65535) {
-    const unsigned nz = (unsigned)std::min<int64_t>(65535, frames - f0);
-    const TX* xf = (const TX*)x + f0 * H * ld;
-    for (int k = 0; k < n; ++k) {
-      if (sides[k] > kViolMaxSide2) return SMRE_EINVAL;
-      if (sides[k] <= kViolMaxSide) {
-        const dim3 grid((unsigned)((W - sides[k] + kViolTileW) / kViolTileW),
-                        (unsigned)((H - sides[k] + kViolTileH) / kViolTileH), nz);
-        hipLaunchKernelGGL((violation_kernel<TX>), grid, dim3(256), 0, s, xf, H * ld, ld,
-                           (int)H, (int)W, sides[k], r2[k], c->ctrl);
-      } else {
-        const dim3 grid((unsigned)((W - sides[k] + kViolTileW2) / kViolTileW2),
-                        (unsigned)((H - sides[k] + kViolTileH2) / kViolTileH2), nz);
-        hipLaunchKernelGGL((violation_kernel<TX, kViolTileH2, kViolTileW2, kViolMaxSide2>), grid,
-                           dim3(256), 0, s, xf, H * ld, ld, (int)H, (int)W, sides[k], r2[k],
-                           c->ctrl);
-      }
-    }
-  }
-  HIP_OK(hipGetLastError());
+  int rc = enqueue_feasibility<TX>(x, H, W, ld, H * ld, frames, n, sides, r2, c->ctrl, s);
+  if (rc) return rc;
   HIP_OK(hipMemcpyAsync(c->ctrl_host, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
   *out = dkey_inv(c->ctrl_host->viol_key);
   return SMRE_OK;
 }
 
+// Non-finite test of the input, enqueued: raises ctrl->nonfinite.
 template <typename TX>
-int check_nonfinite(smre_ctx* c, const void* x, int64_t H, int64_t W, int64_t ld, hipStream_t s,
-                    bool* bad) {
+void enqueue_nonfinite(smre_ctx* c, const void* x, int64_t H, int64_t W, int64_t ld,
+                       hipStream_t s) {
   // every caller gets a cleared flag, whatever the control block held before
   hipLaunchKernelGGL(nonfinite_reset_kernel, dim3(1), dim3(1), 0, s, c->ctrl);
   hipLaunchKernelGGL((nonfinite_kernel<TX>), dim3(grid_rows(H)), dim3(256), 0, s,
                      (const TX*)x, ld, (int)H, (int)W, c->ctrl);
+}
+
+template <typename TX>
+int check_nonfinite(smre_ctx* c, const void* x, int64_t H, int64_t W, int64_t ld, hipStream_t s,
+                    bool* bad) {
+  enqueue_nonfinite<TX>(c, x, H, W, ld, s);
   HIP_OK(hipGetLastError());
   HIP_OK(hipMemcpyAsync(c->ctrl_host, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
@@ -801,23 +843,18 @@ int mc_run_buf(smre_ctx* c, const T* fields, int64_t ld, int64_t H, int64_t W, u
                hipStream_t s, TimingAcc* acc, unsigned long long* tmax, double* q);
 int mc_sides(int32_t n, const int32_t* sides, int64_t H, int64_t W, McSides* sd);
 
-// Device scratch of one ICD call: the work counters (kIcdSlots lines), their
-// sums, and for the single-frame feasibility report the per-level window
-// maxima and the statistic of the frame.
+// Device scratch of one ICD call: the work counters (kIcdSlots lines).  Their
+// sums and the feasibility report go through the context's control block.
 struct IcdScratch {
   unsigned long long* cnt;   // kIcdSlots * kIcdSlotWords words
-  unsigned long long* sum;   // kIcdCountWords words
-  unsigned long long* tmax;  // K + 1 words (one frame)
-  double* q;                 // one double
 };
 constexpr int64_t kIcdCntWords = (int64_t)kIcdSlots * kIcdSlotWords;
-// words of the allocation-free scratch: counters, sums, maxima (K + 1 <= 6,
-// rounded up), the statistic
-constexpr int64_t kIcdScratchWords = kIcdCntWords + 8 + 8 + 8;
+// words of the allocation-free scratch: the counters
+constexpr int64_t kIcdScratchWords = kIcdCntWords;
 
 }  // namespace
 
-// Device scratch of smre_dykstra_incomplete_noalloc (32,960 bytes, held by every
+// Device scratch of smre_dykstra_incomplete_noalloc (32,768 bytes, held by every
 // GPU the library runs on until the process ends).  In host code `scratch`
 // names a host-side stand-in: kernels get its device address, looked up per
 // device with hipGetSymbolAddress when a context is created.
@@ -861,22 +898,19 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t fra
   HIP_OK(hipEventRecord(c->t0, s));
   int rc = SMRE_OK;
   if (checks) {
+    // the non-finite test is enqueued, not waited for: the phase kernels read
+    // its flag and leave x alone when it is raised, and the one wait at the
+    // end of the call reads it with the counters and the feasibility report.
+    // Frames are stacked H * ld elements apart: one tall image of frames * H rows.
     hipLaunchKernelGGL(ctrl_reset_kernel, dim3(1), dim3(1), 0, s, c->ctrl);
-    bool bad = false;
-    // frames are stacked H * ld elements apart: one tall image of frames * H rows
-    rc = check_nonfinite<T>(c, x, frames * H, W, ld, s, &bad);
-    if (rc) return rc;
-    if (bad) return SMRE_ENONFINITE;
+    enqueue_nonfinite<T>(c, x, frames * H, W, ld, s);
   }
-  unsigned long long *cnt, *cnt_sum;
+  unsigned long long* cnt;
   if (fixed) {
     cnt = fixed->cnt;
-    cnt_sum = fixed->sum;
   } else {
-    if (!c->icd_cnt)
-      HIP_OK(hipMalloc(&c->icd_cnt, sizeof(unsigned long long) * (kIcdCntWords + 8)));
+    if (!c->icd_cnt) HIP_OK(hipMalloc(&c->icd_cnt, sizeof(unsigned long long) * kIcdCntWords));
     cnt = c->icd_cnt;
-    cnt_sum = c->icd_cnt + kIcdCntWords;
   }
   hipLaunchKernelGGL((fill_kernel<unsigned long long>), dim3(grid_for(kIcdCntWords)), dim3(256),
                      0, s, cnt, kIcdCntWords, 0ull);
@@ -893,6 +927,7 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t fra
     a.sr2[k] = std::sqrt((float)r2[k]);
   }
   a.counters = cnt;
+  a.skip = checks ? &c->ctrl->nonfinite : nullptr;
   const int B = 1 << K;
   std::optional<TimingAcc> tacc;  // (its queue allocates: not on the fixed path)
   if (!fixed) tacc.emplace();
@@ -932,49 +967,30 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t fra
   }
   // inner sweeps, square projections, (square, pixel) updates, blocks that
   // stopped at max_inner without meeting the tolerance
-  hipLaunchKernelGGL(icd_counter_sum, dim3(1), dim3(kIcdSlots), 0, s, cnt, cnt_sum);
+  hipLaunchKernelGGL(icd_counter_sum, dim3(1), dim3(kIcdSlots), 0, s, cnt, c->ctrl->icd_sum);
   HIP_OK(hipGetLastError());
-  unsigned long long sums[kIcdCountWords];
-  HIP_OK(hipMemcpyAsync(sums, cnt_sum, sizeof sums, hipMemcpyDeviceToHost, s));
-  HIP_OK(hipStreamSynchronize(s));
-  if (tacc && (rc = timing_flush(c, *tacc, true))) return rc;
   // Reported: the violation over the FULL family of the levels' sides (every
   // position, every frame), i.e. how far ICD is from feasibility for the
-  // exact method: the largest window sum of each (frame, side) from the
-  // all-sides tile kernel, then the worst ratio to its bound.
-  double viol = NAN;
+  // exact method.
   if (checks && rep) {  // the feasibility pass only feeds the report
     int32_t fam[6];
     double fam_r2[6];
     int nfam = 0;
-    for (int k = 0; k <= K; ++k)
-      if ((1 << k) <= H && (1 << k) <= W) {
-        fam[nfam] = 1 << k;
-        fam_r2[nfam++] = r2[k];
-      }
-    McSides sd;
-    rc = mc_sides(nfam, fam, H, W, &sd);
-    if (rc) return rc;
-    viol = -INFINITY;
-    if (fixed) {
-      double q1 = 0.0, tm[6];
-      rc = mc_run_buf<false, T>(c, (const T*)x, ld, H, W, 0, 0, 1, sd, &q1, tm, s, nullptr,
-                                fixed->tmax, fixed->q);
-      if (rc) return rc;
-      for (int k = 0; k < nfam; ++k) viol = std::max(viol, tm[k] / fam_r2[k] - 1.0);
-    } else {
-      std::vector<double> qf((size_t)frames), tmax((size_t)frames * nfam);
-      TimingAcc vacc;
-      rc = mc_run<false, T>(c, (const T*)x, ld, H, W, 0, 0, frames, sd, qf.data(), tmax.data(),
-                            s, vacc);
-      if (rc) return rc;
-      for (int64_t f = 0; f < frames; ++f)
-        for (int k = 0; k < nfam; ++k)
-          viol = std::max(viol, tmax[(size_t)f * nfam + k] / fam_r2[k] - 1.0);
+    for (int k = 0; k <= K; ++k) {
+      fam[nfam] = 1 << k;
+      fam_r2[nfam++] = r2[k];
     }
+    rc = enqueue_feasibility<T>(x, H, W, ld, H * ld, frames, nfam, fam, fam_r2, c->ctrl, s);
+    if (rc) return rc;
   }
+  HIP_OK(hipMemcpyAsync(c->ctrl_host, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
   HIP_OK(hipEventRecord(c->t1, s));
   HIP_OK(hipEventSynchronize(c->t1));
+  if (tacc && (rc = timing_flush(c, *tacc, true))) return rc;
+  const Ctrl& fin = *c->ctrl_host;
+  if (checks && fin.nonfinite) return SMRE_ENONFINITE;  // x was left as it came
+  const unsigned long long* sums = fin.icd_sum;
+  const double viol = (checks && rep) ? dkey_inv(fin.viol_key) : NAN;
   float ms = 0.f;
   HIP_OK(hipEventElapsedTime(&ms, c->t0, c->t1));
   if (rep) {
@@ -1110,15 +1126,12 @@ int nested_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t 
                 int nph, const int32_t* sy, const int32_t* sx, const int32_t* lo, hipStream_t s,
                 smre_report* rep) {
   HIP_OK(hipEventRecord(c->t0, s));
+  // non-finite test enqueued, read back with the results (as in icd_impl)
   hipLaunchKernelGGL(ctrl_reset_kernel, dim3(1), dim3(1), 0, s, c->ctrl);
-  bool bad = false;
-  int rc = check_nonfinite<T>(c, x, frames * H, W, ld, s, &bad);
-  if (rc) return rc;
-  if (bad) return SMRE_ENONFINITE;
-  if (!c->icd_cnt)
-    HIP_OK(hipMalloc(&c->icd_cnt, sizeof(unsigned long long) * (kIcdCntWords + 8)));
+  enqueue_nonfinite<T>(c, x, frames * H, W, ld, s);
+  int rc = SMRE_OK;
+  if (!c->icd_cnt) HIP_OK(hipMalloc(&c->icd_cnt, sizeof(unsigned long long) * kIcdCntWords));
   unsigned long long* cnt = c->icd_cnt;
-  unsigned long long* cnt_sum = c->icd_cnt + kIcdCntWords;
   hipLaunchKernelGGL((fill_kernel<unsigned long long>), dim3(grid_for(kIcdCntWords)), dim3(256),
                      0, s, cnt, kIcdCntWords, 0ull);
   NestedArgs a{};
@@ -1138,6 +1151,7 @@ int nested_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t 
     a.sr2[j] = std::sqrt((float)r2[j]);
   }
   a.counters = cnt;
+  a.skip = &c->ctrl->nonfinite;
   const int B = a.B;
   TimingAcc tacc;
   for (int ph = 0; ph < nph; ++ph) {
@@ -1160,31 +1174,22 @@ int nested_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t 
     }
     if ((rc = timing_end(c, tacc, s, slot))) return rc;
   }
-  hipLaunchKernelGGL(icd_counter_sum, dim3(1), dim3(kIcdSlots), 0, s, cnt, cnt_sum);
+  hipLaunchKernelGGL(icd_counter_sum, dim3(1), dim3(kIcdSlots), 0, s, cnt, c->ctrl->icd_sum);
   HIP_OK(hipGetLastError());
-  unsigned long long sums[kIcdCountWords];
-  HIP_OK(hipMemcpyAsync(sums, cnt_sum, sizeof sums, hipMemcpyDeviceToHost, s));
-  HIP_OK(hipStreamSynchronize(s));
-  if ((rc = timing_flush(c, tacc, true))) return rc;
   // reported: the violation over the full family of the levels' sides (every
   // position, every frame)
-  double viol = NAN;
   if (rep) {
-    int fam[kNestLevels];
-    double fam_r2[kNestLevels];
-    int nfam = 0;
-    for (int j = 0; j < nlev; ++j)
-      if (side[j] <= H && side[j] <= W) {
-        fam[nfam] = side[j];
-        fam_r2[nfam++] = r2[j];
-      }
-    if (nfam > 0) {
-      rc = run_violation<T>(c, x, H, W, ld, nfam, fam, fam_r2, s, &viol, frames);
-      if (rc) return rc;
-    }
+    rc = enqueue_feasibility<T>(x, H, W, ld, H * ld, frames, nlev, side, r2, c->ctrl, s);
+    if (rc) return rc;
   }
+  HIP_OK(hipMemcpyAsync(c->ctrl_host, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
   HIP_OK(hipEventRecord(c->t1, s));
   HIP_OK(hipEventSynchronize(c->t1));
+  if ((rc = timing_flush(c, tacc, true))) return rc;
+  const Ctrl& fin = *c->ctrl_host;
+  if (fin.nonfinite) return SMRE_ENONFINITE;  // x was left as it came
+  const unsigned long long* sums = fin.icd_sum;
+  const double viol = rep ? dkey_inv(fin.viol_key) : NAN;
   float ms = 0.f;
   HIP_OK(hipEventElapsedTime(&ms, c->t0, c->t1));
   if (rep) {
@@ -1918,15 +1923,9 @@ class HipBackend : public smre_serve::Backend {
     r.rep.last_delta = sl.last.last_delta;
     double worst = 0.0;
     hipLaunchKernelGGL(ctrl_reset_kernel, dim3(1), dim3(1), 0, stream_, vctrl_);
-    for (int k = 0; k < sl.plan.nsides; ++k) {
-      const int sk = sl.plan.sides[k];
-      const dim3 grid((unsigned)((r.W - sk + kViolTileW) / kViolTileW),
-                      (unsigned)((r.H - sk + kViolTileH) / kViolTileH));
-      hipLaunchKernelGGL((violation_kernel<float>), grid, dim3(256), 0, stream_,
-                         (const float*)sl.desc.x, (int64_t)0, (int64_t)r.W, r.H, r.W, sk,
-                         sl.plan.r2[k], vctrl_);
-    }
-    HIP_OK(hipGetLastError());
+    const int vrc = enqueue_feasibility<float>(sl.desc.x, r.H, r.W, r.W, 0, 1, sl.plan.nsides,
+                                               sl.plan.sides, sl.plan.r2, vctrl_, stream_);
+    if (vrc) return vrc;
     Ctrl vc;
     HIP_OK(hipMemcpyAsync(&vc, vctrl_, sizeof(Ctrl), hipMemcpyDeviceToHost, stream_));
     HIP_OK(hipStreamSynchronize(stream_));
@@ -2622,15 +2621,12 @@ int smre_dykstra_incomplete_noalloc(smre_ctx* c, smre_dtype dt, void* x, int64_t
   }
   int rc = icd_validate(c, dt, x, H, W, ld, 1, K, r2, nph, sy, sx, lo, tol, mode, max_inner);
   if (rc) return rc;
-  // the scratch holds the counters, their sums, one maximum per level (at
-  // most 8) and one statistic, whatever the image size
-  if (K + 1 > 8) return SMRE_ETOOBIG;
+  // the scratch holds the work counters, whatever the image size
   rc = set_device(c);
   if (rc) return rc;
   unsigned long long* base = scratch_of(c->device);
   if (!base) return SMRE_EDEVICE;  // set up when the context was created
-  const IcdScratch fs{base, base + kIcdCntWords, base + kIcdCntWords + 8,
-                      (double*)(base + kIcdCntWords + 16)};
+  const IcdScratch fs{base};
   hipStream_t s = (hipStream_t)stream;
   if (dt == SMRE_F64)
     return icd_impl<double>(c, x, H, W, ld, 1, K, r2, tol, mode, max_inner, nph, sy, sx, lo, s,
@@ -2686,7 +2682,8 @@ int smre_max_violation(smre_ctx* c, smre_dtype dt, const void* x, int64_t H, int
   if (!c || !x || !sides || !r2 || !out || n < 1) return SMRE_EINVAL;
   if (H < 1 || W < 1 || ld < W) return SMRE_EINVAL;
   for (int k = 0; k < n; ++k) {
-    if (sides[k] < 1 || sides[k] > H || sides[k] > W) return SMRE_EINVAL;
+    if (sides[k] < 1 || sides[k] > H || sides[k] > W || sides[k] > kViolMaxSide)
+      return SMRE_EINVAL;
     if (!(r2[k] > 0) || !std::isfinite(r2[k])) return SMRE_EINVAL;
   }
   int rc = set_device(c);

@@ -302,8 +302,9 @@ def test_max_violation_matches_oracle(ctx):
 
 @pytest.mark.parametrize("side", [1, 5, 17, 31, 32])
 def test_max_violation_tiles_and_edges(ctx, side):
-    """Several 32 x 64 anchor tiles with ragged last tiles, each side alone (so
-    the reported maximum is that side's), FP64 and FP32 images."""
+    """Several anchor tiles (64 x 64 up to side 16, 32 x 64 up to 32) with
+    ragged last tiles, each side alone (so the reported maximum is that
+    side's), FP64 and FP32 images."""
     z = gi.emitters(150, 203, n_e=40, seed=11)
     r2 = oracle.chi2_bounds([side])
     want = oracle.max_violation(z, [side], r2)
@@ -313,6 +314,61 @@ def test_max_violation_tiles_and_edges(ctx, side):
     want32 = oracle.max_violation(z32.astype(np.float64), [side], r2)
     got32 = ctx.max_violation(dev(z32, torch.float32), [side], r2)
     assert got32 == pytest.approx(want32, rel=1e-12, abs=1e-14)
+
+
+def rowcol_violation(z, sides, r2):
+    """max over windows of sum z^2 / r2 - 1 with each window's sum taken as its
+    row sums (left to right) added top to bottom, in FP64: the order the
+    library's feasibility kernels use, so the result must match to the bit."""
+    sq = np.asarray(z, dtype=np.float64) ** 2
+    H, W = sq.shape
+    worst = -1.0
+    for s, r in zip(sides, r2):
+        if s > H or s > W:
+            continue
+        h = np.zeros((H, W - s + 1))
+        for j in range(s):
+            h = h + sq[:, j:j + W - s + 1]
+        n = np.zeros((H - s + 1, W - s + 1))
+        for k in range(s):
+            n = n + h[k:k + H - s + 1, :]
+        worst = max(worst, float(n.max()) / r - 1.0)
+    return worst
+
+
+@pytest.mark.parametrize("H,W,sides", [
+    (150, 203, [1, 2, 4, 8]),                 # sides up to 8, ragged 64 x 64 tiles
+    (131, 260, list(range(1, 17))),           # up to 16
+    (97, 140, [1, 3, 17, 31, 32]),            # up to 32 (32 x 64 tiles)
+    (140, 150, [1, 5, 33, 48, 64, 96]),       # longer sides, one launch each
+    (40, 300, [2, 7, 40]),                    # a side equal to the height
+])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_max_violation_bitwise_rowcol(ctx, H, W, sides, dtype):
+    z = gi.emitters(H, W, n_e=max(3, H * W // 600), seed=H + W) + 0.7 * gi.gaussian(H, W, seed=3)
+    if dtype == torch.float32:
+        z = z.astype(np.float32).astype(np.float64)
+    r2 = oracle.chi2_bounds(sides)
+    got = ctx.max_violation(dev(z, dtype), sides, r2)
+    assert got == rowcol_violation(z, sides, r2)
+    assert got == pytest.approx(oracle.max_violation(z, sides, r2), rel=1e-12, abs=1e-14)
+
+
+def test_max_violation_side_listed_twice(ctx):
+    """A side listed with two bounds is held to the smaller one."""
+    z = gi.emitters(64, 90, n_e=8, seed=2)
+    got = ctx.max_violation(dev(z), [4, 2, 4], [30.0, 8.0, 20.0])
+    assert got == rowcol_violation(z, [2, 4], [8.0, 20.0])
+
+
+def test_max_violation_strided_fp32(ctx):
+    z = gi.emitters(77, 100, n_e=10, seed=6).astype(np.float32)
+    big = torch.zeros(77, 128, dtype=torch.float32, device="cuda")
+    big[:, :100] = torch.from_numpy(z).cuda()
+    sides = [1, 2, 3, 5, 9]
+    r2 = oracle.chi2_bounds(sides)
+    got = ctx.max_violation(big[:, :100], sides, r2)
+    assert got == rowcol_violation(z.astype(np.float64), sides, r2)
 
 
 # ----------------------------------------------------------------- full size
