@@ -257,7 +257,7 @@ __global__ __launch_bounds__(256) void increment_sum_kernel(const TX* x, int64_t
       isum[(int64_t)r * W + col] -= x[(int64_t)r * ld + col];
 }
 
-__global__ void ctrl_reset_kernel(Ctrl* c) {
+__device__ __forceinline__ void ctrl_reset(Ctrl* c) {
   c->done = 0;
   c->done_sweep = 0;
   c->nonfinite = 0;
@@ -265,6 +265,18 @@ __global__ void ctrl_reset_kernel(Ctrl* c) {
   c->delta_key = dkey(0.0);
   c->last_delta = -1.0;
   c->viol_key = dkey(-1.0);
+}
+
+__global__ void ctrl_reset_kernel(Ctrl* c) { ctrl_reset(c); }
+
+// Start of an ICD call in one launch: the work counters cleared and, when
+// `reset`, the control block reset (before the input check raises its flag).
+__global__ __launch_bounds__(256) void icd_begin_kernel(Ctrl* c, int reset,
+                                                        unsigned long long* cnt, int64_t n) {
+  if (reset && blockIdx.x == 0 && threadIdx.x == 0) ctrl_reset(c);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    cnt[i] = 0;
 }
 
 // ---------------------------------------------------------------- batch control

@@ -470,12 +470,13 @@ int run_violation(smre_ctx* c, const void* x, int64_t H, int64_t W, int64_t ld, 
   return SMRE_OK;
 }
 
-// Non-finite test of the input, enqueued: raises ctrl->nonfinite.
+// Non-finite test of the input, enqueued: raises ctrl->nonfinite.  `clear`:
+// clear the flag first (false: the caller has reset the control block).
 template <typename TX>
 void enqueue_nonfinite(smre_ctx* c, const void* x, int64_t H, int64_t W, int64_t ld,
-                       hipStream_t s) {
+                       hipStream_t s, bool clear = true) {
   // every caller gets a cleared flag, whatever the control block held before
-  hipLaunchKernelGGL(nonfinite_reset_kernel, dim3(1), dim3(1), 0, s, c->ctrl);
+  if (clear) hipLaunchKernelGGL(nonfinite_reset_kernel, dim3(1), dim3(1), 0, s, c->ctrl);
   hipLaunchKernelGGL((nonfinite_kernel<TX>), dim3(grid_rows(H)), dim3(256), 0, s,
                      (const TX*)x, ld, (int)H, (int)W, c->ctrl);
 }
@@ -897,14 +898,6 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t fra
   if (fixed && frames != 1) return SMRE_EINVAL;
   HIP_OK(hipEventRecord(c->t0, s));
   int rc = SMRE_OK;
-  if (checks) {
-    // the non-finite test is enqueued, not waited for: the phase kernels read
-    // its flag and leave x alone when it is raised, and the one wait at the
-    // end of the call reads it with the counters and the feasibility report.
-    // Frames are stacked H * ld elements apart: one tall image of frames * H rows.
-    hipLaunchKernelGGL(ctrl_reset_kernel, dim3(1), dim3(1), 0, s, c->ctrl);
-    enqueue_nonfinite<T>(c, x, frames * H, W, ld, s);
-  }
   unsigned long long* cnt;
   if (fixed) {
     cnt = fixed->cnt;
@@ -912,8 +905,14 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t fra
     if (!c->icd_cnt) HIP_OK(hipMalloc(&c->icd_cnt, sizeof(unsigned long long) * kIcdCntWords));
     cnt = c->icd_cnt;
   }
-  hipLaunchKernelGGL((fill_kernel<unsigned long long>), dim3(grid_for(kIcdCntWords)), dim3(256),
-                     0, s, cnt, kIcdCntWords, 0ull);
+  // counters cleared and the control block reset in one launch; the
+  // non-finite test is enqueued, not waited for: the phase kernels read its
+  // flag and leave x alone when it is raised, and the one wait at the end of
+  // the call reads it with the counters and the feasibility report.  Frames
+  // are stacked H * ld elements apart: one tall image of frames * H rows.
+  hipLaunchKernelGGL(icd_begin_kernel, dim3(grid_for(kIcdCntWords)), dim3(256), 0, s, c->ctrl,
+                     checks ? 1 : 0, cnt, kIcdCntWords);
+  if (checks) enqueue_nonfinite<T>(c, x, frames * H, W, ld, s, false);
   IcdArgs a{};
   a.ld = ld;
   a.fstride = H * ld;
@@ -1126,14 +1125,14 @@ int nested_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t 
                 int nph, const int32_t* sy, const int32_t* sx, const int32_t* lo, hipStream_t s,
                 smre_report* rep) {
   HIP_OK(hipEventRecord(c->t0, s));
-  // non-finite test enqueued, read back with the results (as in icd_impl)
-  hipLaunchKernelGGL(ctrl_reset_kernel, dim3(1), dim3(1), 0, s, c->ctrl);
-  enqueue_nonfinite<T>(c, x, frames * H, W, ld, s);
   int rc = SMRE_OK;
   if (!c->icd_cnt) HIP_OK(hipMalloc(&c->icd_cnt, sizeof(unsigned long long) * kIcdCntWords));
   unsigned long long* cnt = c->icd_cnt;
-  hipLaunchKernelGGL((fill_kernel<unsigned long long>), dim3(grid_for(kIcdCntWords)), dim3(256),
-                     0, s, cnt, kIcdCntWords, 0ull);
+  // counters cleared and control block reset in one launch, the non-finite
+  // test enqueued and read back with the results (as in icd_impl)
+  hipLaunchKernelGGL(icd_begin_kernel, dim3(grid_for(kIcdCntWords)), dim3(256), 0, s, c->ctrl, 1,
+                     cnt, kIcdCntWords);
+  enqueue_nonfinite<T>(c, x, frames * H, W, ld, s, false);
   NestedArgs a{};
   rc = nested_tables(nlev, side, &a);
   if (rc) return rc;
