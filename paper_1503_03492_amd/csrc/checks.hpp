@@ -131,14 +131,24 @@ __global__ __launch_bounds__(256) void feasibility_kernel(const TX* __restrict__
   __shared__ double sq[ER][EC];
   x += (int64_t)blockIdx.z * fstride;
   const int a0 = blockIdx.y * (4 * RPL), b0 = blockIdx.x * 64;
-  for (int i = threadIdx.x; i < ER * EC; i += 256) {
+  // every load of the lane issued before the first is used (a fixed trip
+  // count, unrolled), so their latencies overlap
+  constexpr int NLD = (ER * EC + 255) / 256;
+  TX v[NLD];
+#pragma unroll
+  for (int u = 0; u < NLD; ++u) {
+    const int i = threadIdx.x + 256 * u;
     const int r = i / EC, cc = i - (i / EC) * EC;
-    double v = 0.0;
-    if (a0 + r < H && b0 + cc < W) {
-      v = (double)x[(int64_t)(a0 + r) * ld + b0 + cc];
-      v = v * v;
+    v[u] = TX(0);
+    if (i < ER * EC && a0 + r < H && b0 + cc < W) v[u] = x[(int64_t)(a0 + r) * ld + b0 + cc];
+  }
+#pragma unroll
+  for (int u = 0; u < NLD; ++u) {
+    const int i = threadIdx.x + 256 * u;
+    if (i < ER * EC) {
+      const double d = (double)v[u];
+      sq[i / EC][i - (i / EC) * EC] = d * d;
     }
-    sq[r][cc] = v;
   }
   __syncthreads();
   const int c = threadIdx.x & 63, r0 = (threadIdx.x >> 6) * RPL;
