@@ -260,6 +260,24 @@ __device__ __forceinline__ void icd_block(const IcdArgs& a, unsigned tx, unsigne
 
   int it = 0;
   bool met = false;  // the stopping rule held (else the block hit max_inner)
+  // The top level K (K >= 1) spans lanes: its inputs y = x - q[K] and their
+  // group sum n are computed at the end of the previous sweep, before the
+  // stopping test, so that test's wave reduction and this one run side by
+  // side (same values; on stopping they are dropped).
+  constexpr int GK = (1 << (2 * K)) / NPL;  // lanes per top-level square
+  T yt[NPL];
+  T nt = T(0);
+  auto top_inputs = [&]() {
+    if constexpr (K >= 1) {
+#pragma unroll
+      for (int e = 0; e < NPL; ++e) yt[e] = x[e] - q[K][e];
+      T part = T(0);
+#pragma unroll
+      for (int e = 0; e < NPL; ++e) part = fma_t(yt[e], yt[e], part);
+      nt = group_sum<GK>(part);
+    }
+  };
+  top_inputs();
   auto sweeps = [&](auto interior_tag) {
     constexpr bool IN = decltype(interior_tag)::value;
     while (true) {
@@ -270,39 +288,48 @@ __device__ __forceinline__ void icd_block(const IcdArgs& a, unsigned tx, unsigne
         const T r2 = (T)a.r2[k];
         const T sr2 = (T)a.sr2[k];
         T y[NPL], xn[NPL];
-#pragma unroll
-        for (int e = 0; e < NPL; ++e) y[e] = x[e] - q[k][e];
         const int sq = 1 << (2 * k);  // pixels per square
-        if (k == 0) {
+        if (k == K && K >= 1) {
+          const T tt = ball_scale(nt, r2, sr2);
 #pragma unroll
-          for (int e = 0; e < NPL; ++e) xn[e] = clamp_t(y[e], c0);
-        } else if (sq <= NPL) {
-          // squares inside one lane: consecutive runs of sq Morton indices
-#pragma unroll
-          for (int e0 = 0; e0 < NPL; e0 += sq) {
-            T n = T(0);
-#pragma unroll
-            for (int e = e0; e < e0 + sq; ++e) n = fma_t(y[e], y[e], n);
-            const T tt = ball_scale(n, r2, sr2);
-#pragma unroll
-            for (int e = e0; e < e0 + sq; ++e) xn[e] = tt * y[e];
+          for (int e = 0; e < NPL; ++e) {
+            y[e] = yt[e];
+            xn[e] = tt * y[e];
           }
         } else {
-          T part = T(0);
 #pragma unroll
-          for (int e = 0; e < NPL; ++e) part = fma_t(y[e], y[e], part);
-          T n;
-          switch (sq / NPL) {
-            case 2: n = group_sum<2>(part); break;
-            case 4: n = group_sum<4>(part); break;
-            case 8: n = group_sum<8>(part); break;
-            case 16: n = group_sum<16>(part); break;
-            case 32: n = group_sum<32>(part); break;
-            default: n = group_sum<64>(part); break;
+          for (int e = 0; e < NPL; ++e) y[e] = x[e] - q[k][e];
+          if (k == 0) {
+#pragma unroll
+            for (int e = 0; e < NPL; ++e) xn[e] = clamp_t(y[e], c0);
+          } else if (sq <= NPL) {
+            // squares inside one lane: consecutive runs of sq Morton indices
+#pragma unroll
+            for (int e0 = 0; e0 < NPL; e0 += sq) {
+              T n = T(0);
+#pragma unroll
+              for (int e = e0; e < e0 + sq; ++e) n = fma_t(y[e], y[e], n);
+              const T tt = ball_scale(n, r2, sr2);
+#pragma unroll
+              for (int e = e0; e < e0 + sq; ++e) xn[e] = tt * y[e];
+            }
+          } else {
+            T part = T(0);
+#pragma unroll
+            for (int e = 0; e < NPL; ++e) part = fma_t(y[e], y[e], part);
+            T n;
+            switch (sq / NPL) {
+              case 2: n = group_sum<2>(part); break;
+              case 4: n = group_sum<4>(part); break;
+              case 8: n = group_sum<8>(part); break;
+              case 16: n = group_sum<16>(part); break;
+              case 32: n = group_sum<32>(part); break;
+              default: n = group_sum<64>(part); break;
+            }
+            const T tt = ball_scale(n, r2, sr2);
+#pragma unroll
+            for (int e = 0; e < NPL; ++e) xn[e] = tt * y[e];
           }
-          const T tt = ball_scale(n, r2, sr2);
-#pragma unroll
-          for (int e = 0; e < NPL; ++e) xn[e] = tt * y[e];
         }
 #pragma unroll
         for (int e = 0; e < NPL; ++e) {
@@ -316,6 +343,7 @@ __device__ __forceinline__ void icd_block(const IcdArgs& a, unsigned tx, unsigne
         }
       }
       ++it;
+      top_inputs();  // the next sweep's, beside the stopping test's reduction
       bool stop;
       if (MEANABS) {
         // FP32 images: the lane sums of |dx| are FP32 already, so the wave
