@@ -54,14 +54,43 @@ struct NestedArgs {
 
 // Sum of v over the aligned group of G lanes containing this one; every lane
 // of a group gets the same bits.  gi = lane index inside its group.  Uniform
-// in G across the workgroup (the LDS path has barriers).
-template <typename T>
-__device__ __forceinline__ T nested_group_sum(T v, int G, int gi, int t, int nt, T* part) {
-  if ((G & (G - 1)) == 0 && G <= 64) {
-    // butterflies: lane a adds lane a ^ o; addition commutes, so both get the
-    // same value at every step
-    for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o);
-    return v;
+// in G across the workgroup (the LDS paths have barriers).
+//
+// G a power of two: DPP and permlane steps inside the wave (lane a with lane
+// a ^ 1, then a ^ 2, ...), and for G > 64 the wave totals of the group added
+// as a pairwise tree after one barrier: the pairs the binary tree over lanes
+// forms, so the same bits.  The wave totals go to wsum[par] and par flips, so
+// the next call writes the other half (every lane has passed this call's
+// barrier before it reads the other half again, at the next call's).
+// Otherwise a binary tree over the lanes in LDS, a barrier per step.
+template <typename T, int MAXW>  // MAXW: the most waves a workgroup has
+__device__ __forceinline__ T nested_group_sum(T v, int G, int gi, int t, int nt, T* part,
+                                              T (*wsum)[16], int& par) {
+  if ((G & (G - 1)) == 0) {
+    switch (G) {
+      case 1: return v;
+      case 2: return group_sum<2>(v);
+      case 4: return group_sum<4>(v);
+      case 8: return group_sum<8>(v);
+      case 16: return group_sum<16>(v);
+      case 32: return group_sum<32>(v);
+      default: break;
+    }
+    v = group_sum<64>(v);
+    if (G == 64) return v;
+    const int gw = G >> 6, w0 = (t - gi) >> 6;  // waves of the group, its first
+    if ((t & 63) == 0) wsum[par][t >> 6] = v;
+    __syncthreads();
+    T w[MAXW];
+#pragma unroll
+    for (int i = 0; i < MAXW; ++i) w[i] = i < gw ? wsum[par][w0 + i] : T(0);
+#pragma unroll
+    for (int s = 1; s < MAXW; s <<= 1)
+#pragma unroll
+      for (int i = 0; i + s < MAXW; i += 2 * s)
+        if (i + s < gw) w[i] = w[i] + w[i + s];
+    par ^= 1;
+    return w[0];
   }
   part[t] = v;
   __syncthreads();
@@ -81,6 +110,8 @@ void icd_nested_phase(NestedArgs a) {
   __shared__ T part[1024];
   __shared__ T wred[2][16];
   __shared__ unsigned long long wcnt[16][2];
+  __shared__ T wsum[2][16];  // wave totals of the power-of-two group sums
+  int wpar = 0;
   const int t = threadIdx.x;
   const int nwaves = (blockDim.x + 63) >> 6;
   const int wave = t >> 6, lane = t & 63;
@@ -185,7 +216,8 @@ void icd_nested_phase(NestedArgs a) {
         T ps = T(0);
 #pragma unroll
         for (int e = 0; e < P; ++e) ps = fma_t(y[e], y[e], ps);
-        const T sum = nested_group_sum<T>(ps, a.grp[j], gidx[j], t, a.nt, part);
+        const T sum = nested_group_sum<T, (P == 16 ? 256 : P == 9 ? 512 : 1024) / 64>(
+            ps, a.grp[j], gidx[j], t, a.nt, part, wsum, wpar);
 #pragma unroll
         for (int e = 0; e < P; ++e) n[e] = sum;
       }
@@ -204,10 +236,13 @@ void icd_nested_phase(NestedArgs a) {
     // the block's stopping rule, the same decision in every lane: wave
     // butterflies, then the wave results in wave order
     T v = dacc;
-    for (int o = 32; o > 0; o >>= 1) {
-      const T w = __shfl_xor(v, o);
-      if constexpr (MEANABS) v += w;
-      else v = v > w ? v : w;
+    if constexpr (MEANABS) {
+      v = group_sum<64>(v);
+    } else {
+      for (int o = 32; o > 0; o >>= 1) {
+        const T w = __shfl_xor(v, o);
+        v = v > w ? v : w;
+      }
     }
     if (lane == 0) wred[it & 1][wave] = v;
     __syncthreads();
