@@ -185,27 +185,42 @@ __global__ __launch_bounds__(256) void feasibility_kernel(const TX* __restrict__
 // Sides above kFeasMaxSide, one launch per side: a block takes 16 x 32 window
 // anchors, stages the squares of the (16 + s - 1) x (32 + s - 1) pixels in LDS,
 // sums each row over s columns, then those row sums over s rows (O(s) adds
-// per window instead of s^2 loads).
+// per window instead of s^2 loads).  MAXS: the longest side of the instance
+// (its LDS size: two blocks per CU fit with MAXS = 64).
 constexpr int kViolTileH = 16, kViolTileW = 32, kViolMaxSide = 96;
-template <typename TX>
+template <typename TX, int MAXS>
 __global__ __launch_bounds__(256) void violation_kernel(const TX* x, int64_t fstride, int64_t ld,
                                                         int H, int W, int s, double r2,
                                                         Ctrl* ctrl) {
   x += (int64_t)blockIdx.z * fstride;
-  constexpr int RT = kViolTileH + kViolMaxSide - 1, CT = kViolTileW + kViolMaxSide - 1;
+  constexpr int RT = kViolTileH + MAXS - 1, CT = kViolTileW + MAXS - 1;
   __shared__ double sq[RT][CT];
   __shared__ double hs[RT][kViolTileW];
   const int a0 = blockIdx.y * kViolTileH, b0 = blockIdx.x * kViolTileW;
   const int rows = kViolTileH + s - 1, cols = kViolTileW + s - 1;
-  for (int i = threadIdx.x; i < rows * cols; i += blockDim.x) {
-    const int r = i / cols, cc = i - (i / cols) * cols;
-    const int gr = a0 + r, gc = b0 + cc;
-    double v = 0.0;
-    if (gr < H && gc < W) {
-      v = (double)x[(int64_t)gr * ld + gc];
-      v = v * v;
-    }
-    sq[r][cc] = v;
+  // a wave per row, lanes along it (no index division); four rows' loads
+  // issued before the first is used
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  for (int r0 = wv; r0 < rows; r0 += 16) {
+    TX v[4][(CT + 63) / 64];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < (CT + 63) / 64; ++k) {
+        const int r = r0 + 4 * u, cc = ln + 64 * k;
+        const int gr = a0 + r, gc = b0 + cc;
+        v[u][k] = (r < rows && cc < cols && gr < H && gc < W) ? x[(int64_t)gr * ld + gc] : TX(0);
+      }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < (CT + 63) / 64; ++k) {
+        const int r = r0 + 4 * u, cc = ln + 64 * k;
+        if (r < rows && cc < cols) {
+          const double d = (double)v[u][k];
+          sq[r][cc] = d * d;
+        }
+      }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < rows * kViolTileW; i += blockDim.x) {

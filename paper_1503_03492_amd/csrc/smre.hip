@@ -450,8 +450,12 @@ int enqueue_feasibility(const void* x, int64_t H, int64_t W, int64_t ld, int64_t
     for (int k : longer) {
       const dim3 grid((unsigned)((W - sides[k] + kViolTileW) / kViolTileW),
                       (unsigned)((H - sides[k] + kViolTileH) / kViolTileH), nz);
-      hipLaunchKernelGGL((violation_kernel<TX>), grid, dim3(256), 0, s, xf, fstride, ld, (int)H,
-                         (int)W, sides[k], r2[k], ctrl);
+      if (sides[k] <= 64)
+        hipLaunchKernelGGL((violation_kernel<TX, 64>), grid, dim3(256), 0, s, xf, fstride, ld,
+                           (int)H, (int)W, sides[k], r2[k], ctrl);
+      else
+        hipLaunchKernelGGL((violation_kernel<TX, kViolMaxSide>), grid, dim3(256), 0, s, xf,
+                           fstride, ld, (int)H, (int)W, sides[k], r2[k], ctrl);
     }
   }
   HIP_OK(hipGetLastError());
