@@ -138,8 +138,12 @@ const char* smre_status_string(int status);
 /* Context bound to `device` (a HIP device ordinal). */
 int smre_ctx_create(int device, smre_ctx** out);
 void smre_ctx_destroy(smre_ctx* ctx);
-/* Record HIP events around every sweep kernel (reported in smre_report). */
-int smre_ctx_set_timing(smre_ctx* ctx, int on);
+/* Record HIP events around the sweep kernels (reported in smre_report as
+ * kernel_ms and kernel_launches): every = 0 off, 1 around every launch, k > 1
+ * around every k-th launch of a call (each event pair costs a launch gap, so a
+ * long solve can be timed on a sample; kernel_ms and kernel_launches then
+ * cover the timed launches only).  SMRE_EINVAL for every < 0. */
+int smre_ctx_set_timing(smre_ctx* ctx, int every);
 
 /* Window bounds on the host: chi-square(s*s degrees of freedom) p-quantile
  * for each side, i.e. the bound that i.i.d. N(0,1) noise meets with

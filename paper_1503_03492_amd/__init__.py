@@ -291,7 +291,10 @@ class Context:
             pass
 
     def set_timing(self, on):
-        _check(_lib.smre_ctx_set_timing(self._h, 1 if on else 0), "smre_ctx_set_timing")
+        """on: False / True (every sweep-kernel launch), or k >= 1 (every k-th
+        launch of a call)."""
+        every = (1 if on else 0) if isinstance(on, bool) else int(on)
+        _check(_lib.smre_ctx_set_timing(self._h, every), "smre_ctx_set_timing")
 
     @staticmethod
     def _params(sides, radius2, o):

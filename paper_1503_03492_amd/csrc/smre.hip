@@ -88,6 +88,7 @@ int set_device(smre_ctx* c) {
 struct TimingAcc {
   double ms = 0.0;
   int64_t launches = 0;
+  int64_t seen = 0;         // launches offered for timing (every k-th is timed)
   std::deque<int> pending;  // event pair indices in flight
 };
 
@@ -107,6 +108,7 @@ int timing_flush(smre_ctx* c, TimingAcc& acc, bool all) {
 int timing_begin(smre_ctx* c, TimingAcc& acc, hipStream_t s, int* slot) {
   *slot = -1;
   if (!c->timing) return SMRE_OK;
+  if (c->timing > 1 && acc.seen++ % c->timing != 0) return SMRE_OK;  // not sampled
   if ((int)acc.pending.size() >= kTimingPairs) {
     int rc = timing_flush(c, acc, false);
     if (rc) return rc;
@@ -2460,9 +2462,9 @@ void smre_ctx_destroy(smre_ctx* c) {
   delete c;
 }
 
-int smre_ctx_set_timing(smre_ctx* c, int on) {
-  if (!c) return SMRE_EINVAL;
-  c->timing = on ? 1 : 0;
+int smre_ctx_set_timing(smre_ctx* c, int every) {
+  if (!c || every < 0) return SMRE_EINVAL;
+  c->timing = every;
   return SMRE_OK;
 }
 

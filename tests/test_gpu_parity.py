@@ -473,3 +473,24 @@ def test_icd_cap_reported_not_converged(ctx, smre):
     x = dev(x0)
     rep = ctx.incomplete(x, K, r2, tol=1e-13, mode=0, max_inner=100000)
     assert rep["converged"] == 1
+
+
+def test_sampled_kernel_timing(ctx, smre):
+    """set_timing(k): events around every k-th sweep-kernel launch of a call,
+    counted from the first; the image is the same whether timed or not."""
+    x0 = gi.emitters(64, 80, n_e=8, seed=3)
+    sides, r2 = [1, 2, 4], oracle.chi2_bounds([1, 2, 4])
+    outs, reps = [], []
+    for every in (1, 3, 0):
+        ctx.set_timing(every)
+        z, _, rep = gpu_project(ctx, x0, sides, r2, tol=1e-9, max_sweeps=5000)
+        outs.append(z)
+        reps.append(rep)
+    ctx.set_timing(False)
+    total = reps[0]["kernel_launches"]
+    assert total > 3 and reps[0]["kernel_ms"] > 0
+    assert reps[1]["kernel_launches"] == (total + 2) // 3
+    assert reps[2]["kernel_launches"] == 0 and reps[2]["kernel_ms"] == 0
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    with pytest.raises(smre.SmreError):
+        ctx.set_timing(-1)
