@@ -178,7 +178,11 @@ int smre_dykstra_project(smre_ctx* ctx, smre_dtype dtype, void* x, int64_t H, in
  * zeroed at the start of the phase.
  * Returns SMRE_OK, SMRE_NOT_CONVERGED (the result is written, but at least one
  * block stopped at max_inner without meeting tol; report->converged = 0), or
- * an error. */
+ * an error; SMRE_ENONFINITE (NaN or Inf in x) leaves x as it came.  The call
+ * blocks the host once, after its last kernel: the input check runs on the
+ * stream ahead of the phases, which leave x alone when it fails.  report (may
+ * be NULL): counters, and max_violation over every window of the levels'
+ * sides (a pass over x that is skipped when report is NULL). */
 int smre_dykstra_incomplete(smre_ctx* ctx, smre_dtype dtype, void* x, int64_t H, int64_t W,
                             int64_t ld, int32_t K, const double* radius2, double tol,
                             int32_t tolmode, int32_t max_inner, int32_t num_phases, void* stream,
