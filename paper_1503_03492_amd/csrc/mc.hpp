@@ -75,17 +75,18 @@ __device__ __forceinline__ void mc_group(uint64_t seed, int64_t f, int64_t g, un
                                          double z[4]) {
   uint64_t c0 = (uint64_t)g, c1 = (uint64_t)f, c2 = 0, c3 = 0;
   philox4x64_10(c0, c1, c2, c3, seed, 0);
+  constexpr double kLn2 = 0.6931471805599453;  // ln u = ln 2 * log2 u
   // the angle 2 pi u as sincospi(2 u): 2 u is exact, so the reduction is
   // exact and cheap (within an ulp or so of sin/cos of the rounded 2 pi u)
   if (need & 3u) {
-    const double r = sqrt(-2.0 * log(mc_unit(c0)));
+    const double r = sqrt(-2.0 * kLn2 * log2(mc_unit(c0)));
     double sn, cs;
     sincospi(2.0 * mc_unit(c1), &sn, &cs);
     z[0] = r * cs;
     z[1] = r * sn;
   }
   if (need & 12u) {
-    const double r = sqrt(-2.0 * log(mc_unit(c2)));
+    const double r = sqrt(-2.0 * kLn2 * log2(mc_unit(c2)));
     double sn, cs;
     sincospi(2.0 * mc_unit(c3), &sn, &cs);
     z[2] = r * cs;
