@@ -37,6 +37,7 @@ struct Ctrl {
   double last_delta;
   unsigned long long viol_key;   // running max violation
   unsigned long long icd_sum[4]; // an ICD call's summed work counters
+  unsigned int nf_epoch;         // last ICD call (by its number) whose input was not finite
 };
 
 template <typename TX>
@@ -294,14 +295,34 @@ __device__ __forceinline__ void ctrl_reset(Ctrl* c) {
 
 __global__ void ctrl_reset_kernel(Ctrl* c) { ctrl_reset(c); }
 
-// Start of an ICD call in one launch: the work counters cleared and, when
-// `reset`, the control block reset (before the input check raises its flag).
+// A new control block: reset, and no ICD call has seen a non-finite input.
+__global__ void ctrl_init_kernel(Ctrl* c) {
+  ctrl_reset(c);
+  c->nf_epoch = 0;
+}
+
+// Start of an ICD call in one launch: the work counters cleared; when `reset`,
+// the control block reset; when x is given, its rows scanned for NaN or Inf,
+// which raises nf_epoch to the call's number `epoch`.  The flag needs no
+// clearing (a call's phase kernels compare it with their own number, and the
+// numbers grow), so the scan shares the launch with the reset.
+template <typename TX>
 __global__ __launch_bounds__(256) void icd_begin_kernel(Ctrl* c, int reset,
-                                                        unsigned long long* cnt, int64_t n) {
+                                                        unsigned long long* cnt, int64_t n,
+                                                        const TX* __restrict__ x, int64_t ld,
+                                                        int rows, int W, unsigned epoch) {
   if (reset && blockIdx.x == 0 && threadIdx.x == 0) ctrl_reset(c);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     cnt[i] = 0;
+  if (!x) return;
+  int bad = 0;
+  for (int r = blockIdx.x; r < rows; r += gridDim.x)
+    for (int col = threadIdx.x; col < W; col += blockDim.x) {
+      const double v = (double)x[(int64_t)r * ld + col];
+      bad |= !(v - v == 0.0);
+    }
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicMax(&c->nf_epoch, epoch);
 }
 
 // ---------------------------------------------------------------- batch control

@@ -73,7 +73,7 @@ struct IcdArgs {
   int32_t lmin;       // lowest level projected in this phase
   int32_t mode;       // 0: max |dx| < tol, 1: sum |dx| <= tol * block pixels
   int32_t max_inner;
-  int32_t pad;
+  uint32_t epoch;     // this call's number (see skip)
   double tol;
   double r2[6];
   float sr2[6];       // sqrtf((float)r2[k]) for the FP32 scale
@@ -82,9 +82,9 @@ struct IcdArgs {
   // and (square, pixel) updates to words 0, 1, 2 of slot (block id mod
   // kIcdSlots), so no line takes more than a share of the blocks' atomics.
   unsigned long long* counters;
-  // null, or a flag that the input check before the call raises for a
-  // non-finite input: every block then leaves the image as it is
-  const int* skip;
+  // null, or the number of the last call whose input check found a NaN or
+  // Inf: when it is this call's (epoch), every block leaves the image as it is
+  const unsigned* skip;
   // q = n / d for the launch's gridDim.x and gridDim.x * gridDim.y by a
   // multiply-high and shifts (udiv_magic), so the uniform block-index split
   // costs no VALU division sequence
@@ -375,7 +375,7 @@ __device__ __forceinline__ void icd_block(const IcdArgs& a, unsigned tx, unsigne
 // neighbours (icd_remap).  A wave adds its counts to one counter slot.
 template <typename T, int K, bool MEANABS>
 __global__ __launch_bounds__(64) void icd_phase(IcdArgs a) {
-  if (a.skip && *a.skip) return;
+  if (a.skip && *a.skip == a.epoch) return;
   IcdCount cnt;
   const unsigned w = blockIdx.x;
   if (a.run == 1) {

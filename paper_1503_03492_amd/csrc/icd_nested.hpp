@@ -49,7 +49,8 @@ struct NestedArgs {
   double r2[kNestLevels];
   float sr2[kNestLevels];        // sqrtf((float)r2[j]) for the FP32 scale
   unsigned long long* counters;  // kIcdSlots slots of kIcdSlotWords words (as icd_phase)
-  const int* skip;               // null, or the non-finite input flag (as icd_phase)
+  const unsigned* skip;          // null, or the non-finite input call number (as icd_phase)
+  uint32_t epoch, pad;           // this call's number
 };
 
 // Sum of v over the aligned group of G lanes containing this one; every lane
@@ -106,7 +107,7 @@ __device__ __forceinline__ T nested_group_sum(T v, int G, int gi, int t, int nt,
 template <typename T, int P, bool MEANABS>
 __global__ __launch_bounds__(P == 16 ? 256 : P == 9 ? 512 : 1024)
 void icd_nested_phase(NestedArgs a) {
-  if (a.skip && *a.skip) return;
+  if (a.skip && *a.skip == a.epoch) return;
   __shared__ T part[1024];
   __shared__ T wred[2][16];
   __shared__ unsigned long long wcnt[16][2];

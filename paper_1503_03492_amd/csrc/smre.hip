@@ -58,6 +58,7 @@ struct smre_ctx {
   Ctrl* ctrl = nullptr;       // device control block
   Ctrl* ctrl_host = nullptr;  // pinned mirror ring
   int* counter = nullptr;     // device int (ICD inner sweeps)
+  unsigned icd_epoch = 0;     // number of the last ICD call (its non-finite flag value)
   int timing = 0;
   hipEvent_t ev[2 * kTimingPairs] = {};
   int ev_used = 0;
@@ -346,7 +347,7 @@ void problem_signature(smre_dtype dt, int64_t H, int64_t W, const smre_params* p
 int ensure_ctrl(smre_ctx* c) {
   if (!c->ctrl) {
     HIP_OK(hipMalloc(&c->ctrl, sizeof(Ctrl)));
-    hipLaunchKernelGGL(ctrl_reset_kernel, dim3(1), dim3(1), 0, 0, c->ctrl);  // defined contents
+    hipLaunchKernelGGL(ctrl_init_kernel, dim3(1), dim3(1), 0, 0, c->ctrl);  // defined contents
     HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(0));
     HIP_OK(hipHostMalloc(&c->ctrl_host, sizeof(Ctrl) * (kLag + 2), hipHostMallocDefault));
@@ -476,13 +477,12 @@ int run_violation(smre_ctx* c, const void* x, int64_t H, int64_t W, int64_t ld, 
   return SMRE_OK;
 }
 
-// Non-finite test of the input, enqueued: raises ctrl->nonfinite.  `clear`:
-// clear the flag first (false: the caller has reset the control block).
+// Non-finite test of the input, enqueued: raises ctrl->nonfinite.
 template <typename TX>
 void enqueue_nonfinite(smre_ctx* c, const void* x, int64_t H, int64_t W, int64_t ld,
-                       hipStream_t s, bool clear = true) {
+                       hipStream_t s) {
   // every caller gets a cleared flag, whatever the control block held before
-  if (clear) hipLaunchKernelGGL(nonfinite_reset_kernel, dim3(1), dim3(1), 0, s, c->ctrl);
+  hipLaunchKernelGGL(nonfinite_reset_kernel, dim3(1), dim3(1), 0, s, c->ctrl);
   hipLaunchKernelGGL((nonfinite_kernel<TX>), dim3(grid_rows(H)), dim3(256), 0, s,
                      (const TX*)x, ld, (int)H, (int)W, c->ctrl);
 }
@@ -911,14 +911,17 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t fra
     if (!c->icd_cnt) HIP_OK(hipMalloc(&c->icd_cnt, sizeof(unsigned long long) * kIcdCntWords));
     cnt = c->icd_cnt;
   }
-  // counters cleared and the control block reset in one launch; the
-  // non-finite test is enqueued, not waited for: the phase kernels read its
-  // flag and leave x alone when it is raised, and the one wait at the end of
-  // the call reads it with the counters and the feasibility report.  Frames
-  // are stacked H * ld elements apart: one tall image of frames * H rows.
-  hipLaunchKernelGGL(icd_begin_kernel, dim3(grid_for(kIcdCntWords)), dim3(256), 0, s, c->ctrl,
-                     checks ? 1 : 0, cnt, kIcdCntWords);
-  if (checks) enqueue_nonfinite<T>(c, x, frames * H, W, ld, s, false);
+  // one launch clears the counters, resets the control block and runs the
+  // non-finite test, which is not waited for: the phase kernels read its flag
+  // and leave x alone when it holds this call's number, and the one wait at
+  // the end of the call reads it with the counters and the feasibility
+  // report.  Frames are stacked H * ld elements apart: one tall image of
+  // frames * H rows.
+  const unsigned epoch = ++c->icd_epoch;
+  const int begin_grid = checks ? grid_rows(frames * H) : grid_for(kIcdCntWords);
+  hipLaunchKernelGGL((icd_begin_kernel<T>), dim3(begin_grid), dim3(256), 0, s, c->ctrl,
+                     checks ? 1 : 0, cnt, kIcdCntWords, checks ? (const T*)x : (const T*)nullptr,
+                     ld, (int)(frames * H), (int)W, epoch);
   IcdArgs a{};
   a.ld = ld;
   a.fstride = H * ld;
@@ -932,7 +935,8 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t fra
     a.sr2[k] = std::sqrt((float)r2[k]);
   }
   a.counters = cnt;
-  a.skip = checks ? &c->ctrl->nonfinite : nullptr;
+  a.skip = checks ? &c->ctrl->nf_epoch : nullptr;
+  a.epoch = epoch;
   const int B = 1 << K;
   std::optional<TimingAcc> tacc;  // (its queue allocates: not on the fixed path)
   if (!fixed) tacc.emplace();
@@ -993,7 +997,7 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t fra
   HIP_OK(hipEventSynchronize(c->t1));
   if (tacc && (rc = timing_flush(c, *tacc, true))) return rc;
   const Ctrl& fin = *c->ctrl_host;
-  if (checks && fin.nonfinite) return SMRE_ENONFINITE;  // x was left as it came
+  if (checks && fin.nf_epoch == epoch) return SMRE_ENONFINITE;  // x was left as it came
   const unsigned long long* sums = fin.icd_sum;
   const double viol = (checks && rep) ? dkey_inv(fin.viol_key) : NAN;
   float ms = 0.f;
@@ -1134,11 +1138,11 @@ int nested_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t 
   int rc = SMRE_OK;
   if (!c->icd_cnt) HIP_OK(hipMalloc(&c->icd_cnt, sizeof(unsigned long long) * kIcdCntWords));
   unsigned long long* cnt = c->icd_cnt;
-  // counters cleared and control block reset in one launch, the non-finite
-  // test enqueued and read back with the results (as in icd_impl)
-  hipLaunchKernelGGL(icd_begin_kernel, dim3(grid_for(kIcdCntWords)), dim3(256), 0, s, c->ctrl, 1,
-                     cnt, kIcdCntWords);
-  enqueue_nonfinite<T>(c, x, frames * H, W, ld, s, false);
+  // counters cleared, control block reset and the non-finite test in one
+  // launch, read back with the results (as in icd_impl)
+  const unsigned epoch = ++c->icd_epoch;
+  hipLaunchKernelGGL((icd_begin_kernel<T>), dim3(grid_rows(frames * H)), dim3(256), 0, s, c->ctrl,
+                     1, cnt, kIcdCntWords, (const T*)x, ld, (int)(frames * H), (int)W, epoch);
   NestedArgs a{};
   rc = nested_tables(nlev, side, &a);
   if (rc) return rc;
@@ -1156,7 +1160,8 @@ int nested_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t 
     a.sr2[j] = std::sqrt((float)r2[j]);
   }
   a.counters = cnt;
-  a.skip = &c->ctrl->nonfinite;
+  a.skip = &c->ctrl->nf_epoch;
+  a.epoch = epoch;
   const int B = a.B;
   TimingAcc tacc;
   for (int ph = 0; ph < nph; ++ph) {
@@ -1192,7 +1197,7 @@ int nested_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t 
   HIP_OK(hipEventSynchronize(c->t1));
   if ((rc = timing_flush(c, tacc, true))) return rc;
   const Ctrl& fin = *c->ctrl_host;
-  if (fin.nonfinite) return SMRE_ENONFINITE;  // x was left as it came
+  if (fin.nf_epoch == epoch) return SMRE_ENONFINITE;  // x was left as it came
   const unsigned long long* sums = fin.icd_sum;
   const double viol = rep ? dkey_inv(fin.viol_key) : NAN;
   float ms = 0.f;
