@@ -122,10 +122,16 @@ struct FeasSides {
   int32_t smax;                 // largest requested side
 };
 
+//
+// cslots (may be null): work counters to total in the same launch, slot t's
+// word w at cslots[t * sstride + w] for t < 256 and w < 4; block (0, 0, 0)
+// adds them up after its tile and writes csum[0..3] (integers: any order).
 template <typename TX, int SMAX>
 __global__ __launch_bounds__(256) void feasibility_kernel(const TX* __restrict__ x,
                                                           int64_t fstride, int64_t ld, int H,
-                                                          int W, FeasSides fs, Ctrl* ctrl) {
+                                                          int W, FeasSides fs, Ctrl* ctrl,
+                                                          const unsigned long long* cslots,
+                                                          int sstride, unsigned long long* csum) {
   constexpr int RPL = feas_rows_per_lane(SMAX);
   constexpr int ER = 4 * RPL + SMAX - 1, EC = 64 + SMAX - 1;
   constexpr int ROWS = RPL + SMAX - 1;  // rows one lane's windows touch
@@ -181,6 +187,22 @@ __global__ __launch_bounds__(256) void feasibility_kernel(const TX* __restrict__
   }
   worst = block_max<TX>(worst);
   if (threadIdx.x == 0) key_max(&ctrl->viol_key, dkey(worst));
+  if (cslots && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0) {
+    __shared__ unsigned long long wsum[4][4];
+    unsigned long long v[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      v[w] = cslots[(size_t)threadIdx.x * sstride + w];
+      for (int o = 32; o > 0; o >>= 1) v[w] += __shfl_xor(v[w], o);
+    }
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+      for (int w = 0; w < 4; ++w) wsum[threadIdx.x >> 6][w] = v[w];
+    __syncthreads();
+    if (threadIdx.x < 4)
+      csum[threadIdx.x] = wsum[0][threadIdx.x] + wsum[1][threadIdx.x] + wsum[2][threadIdx.x] +
+                          wsum[3][threadIdx.x];
+  }
 }
 
 // Sides above kFeasMaxSide, one launch per side: a block takes 16 x 32 window

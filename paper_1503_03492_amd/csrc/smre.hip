@@ -413,10 +413,16 @@ int launch_phase_any(smre_dtype dt, int inc, int kahan, int R, int SI, const Ima
 // skipped), folded into ctrl->viol_key as enqueued work on s: sides up to
 // kFeasMaxSide in one pass per launch of up to 65535 frames, longer ones one
 // launch each.  The caller resets viol_key and reads it back.
+//
+// cslots (may be null): an ICD call's work-counter slots (kIcdSlots of
+// kIcdSlotWords words), totalled into csum in the same pass, or by
+// icd_counter_sum when no side is short enough for the one-pass kernel.
 template <typename TX>
 int enqueue_feasibility(const void* x, int64_t H, int64_t W, int64_t ld, int64_t fstride,
                         int64_t frames, int n, const int* sides, const double* r2, Ctrl* ctrl,
-                        hipStream_t s) {
+                        hipStream_t s, const unsigned long long* cslots = nullptr,
+                        unsigned long long* csum = nullptr) {
+  static_assert(kIcdSlots == 256 && kIcdCountWords == 4, "feasibility_kernel sums 256 x 4");
   FeasSides fs;
   std::memset(&fs, 0, sizeof fs);
   int smin = 0;
@@ -440,15 +446,18 @@ int enqueue_feasibility(const void* x, int64_t H, int64_t W, int64_t ld, int64_t
     if (fs.smax > 0) {
       const int tr = feas_tile_rows(fs.smax <= 16 ? 16 : 32);
       const dim3 grid((unsigned)((W - smin + 64) / 64), (unsigned)((H - smin + tr) / tr), nz);
+      const unsigned long long* cs = f0 == 0 ? cslots : nullptr;
       if (fs.smax <= 8)
         hipLaunchKernelGGL((feasibility_kernel<TX, 8>), grid, dim3(256), 0, s, xf, fstride, ld,
-                           (int)H, (int)W, fs, ctrl);
+                           (int)H, (int)W, fs, ctrl, cs, kIcdSlotWords, csum);
       else if (fs.smax <= 16)
         hipLaunchKernelGGL((feasibility_kernel<TX, 16>), grid, dim3(256), 0, s, xf, fstride, ld,
-                           (int)H, (int)W, fs, ctrl);
+                           (int)H, (int)W, fs, ctrl, cs, kIcdSlotWords, csum);
       else
         hipLaunchKernelGGL((feasibility_kernel<TX, 32>), grid, dim3(256), 0, s, xf, fstride, ld,
-                           (int)H, (int)W, fs, ctrl);
+                           (int)H, (int)W, fs, ctrl, cs, kIcdSlotWords, csum);
+    } else if (cslots && f0 == 0) {
+      hipLaunchKernelGGL(icd_counter_sum, dim3(1), dim3(kIcdSlots), 0, s, cslots, csum);
     }
     for (int k : longer) {
       const dim3 grid((unsigned)((W - sides[k] + kViolTileW) / kViolTileW),
@@ -974,13 +983,11 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t fra
     }
     if (tacc && (rc = timing_end(c, *tacc, s, slot))) return rc;
   }
-  // inner sweeps, square projections, (square, pixel) updates, blocks that
-  // stopped at max_inner without meeting the tolerance
-  hipLaunchKernelGGL(icd_counter_sum, dim3(1), dim3(kIcdSlots), 0, s, cnt, c->ctrl->icd_sum);
-  HIP_OK(hipGetLastError());
-  // Reported: the violation over the FULL family of the levels' sides (every
-  // position, every frame), i.e. how far ICD is from feasibility for the
-  // exact method.
+  // The work counters (inner sweeps, square projections, (square, pixel)
+  // updates, blocks that stopped at max_inner without meeting the tolerance)
+  // are totalled in the feasibility pass when there is one.  Reported: the
+  // violation over the FULL family of the levels' sides (every position, every
+  // frame), i.e. how far ICD is from feasibility for the exact method.
   if (checks && rep) {  // the feasibility pass only feeds the report
     int32_t fam[6];
     double fam_r2[6];
@@ -989,8 +996,12 @@ int icd_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t fra
       fam[nfam] = 1 << k;
       fam_r2[nfam++] = r2[k];
     }
-    rc = enqueue_feasibility<T>(x, H, W, ld, H * ld, frames, nfam, fam, fam_r2, c->ctrl, s);
+    rc = enqueue_feasibility<T>(x, H, W, ld, H * ld, frames, nfam, fam, fam_r2, c->ctrl, s, cnt,
+                                c->ctrl->icd_sum);
     if (rc) return rc;
+  } else {
+    hipLaunchKernelGGL(icd_counter_sum, dim3(1), dim3(kIcdSlots), 0, s, cnt, c->ctrl->icd_sum);
+    HIP_OK(hipGetLastError());
   }
   HIP_OK(hipMemcpyAsync(c->ctrl_host, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
   HIP_OK(hipEventRecord(c->t1, s));
@@ -1184,13 +1195,15 @@ int nested_impl(smre_ctx* c, void* x, int64_t H, int64_t W, int64_t ld, int64_t 
     }
     if ((rc = timing_end(c, tacc, s, slot))) return rc;
   }
-  hipLaunchKernelGGL(icd_counter_sum, dim3(1), dim3(kIcdSlots), 0, s, cnt, c->ctrl->icd_sum);
-  HIP_OK(hipGetLastError());
   // reported: the violation over the full family of the levels' sides (every
-  // position, every frame)
+  // position, every frame); the work counters totalled in the same pass
   if (rep) {
-    rc = enqueue_feasibility<T>(x, H, W, ld, H * ld, frames, nlev, side, r2, c->ctrl, s);
+    rc = enqueue_feasibility<T>(x, H, W, ld, H * ld, frames, nlev, side, r2, c->ctrl, s, cnt,
+                                c->ctrl->icd_sum);
     if (rc) return rc;
+  } else {
+    hipLaunchKernelGGL(icd_counter_sum, dim3(1), dim3(kIcdSlots), 0, s, cnt, c->ctrl->icd_sum);
+    HIP_OK(hipGetLastError());
   }
   HIP_OK(hipMemcpyAsync(c->ctrl_host, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
   HIP_OK(hipEventRecord(c->t1, s));
