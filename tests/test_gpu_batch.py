@@ -173,3 +173,25 @@ def test_batch_few_workgroups_walk_many_items(ctx, grid):
         ref, _, _ = oracle.dykstra(x0, sides, r2, tol=0, max_sweeps=2,
                                    order=oracle.ORDER_REGION, region=16)
         assert np.max(np.abs(x.cpu().numpy() - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_batch_sampled_timing(ctx):
+    """set_timing(k) on a batch: events around every k-th sweep graph of the
+    call; the images are the same whether timed or not."""
+    sides = list(range(1, 9))
+    r2 = oracle.chi2_bounds(sides)
+    x0s = images(np.float32)
+    outs, reps = [], []
+    for every in (1, 2, 0):
+        ctx.set_timing(every)
+        xs = [dev(x, torch.float32) for x in x0s]
+        rc, rr = ctx.project_batch(xs, sides, r2, tol=1e-5, max_sweeps=4000, region=16)
+        outs.append(xs)
+        reps.append(rr[0])
+    ctx.set_timing(False)
+    total = reps[0]["kernel_launches"]
+    assert total > 2 and reps[0]["kernel_ms"] > 0
+    assert reps[1]["kernel_launches"] == (total + 1) // 2
+    assert reps[2]["kernel_launches"] == 0
+    for k in range(len(x0s)):
+        assert torch.equal(outs[0][k], outs[1][k]) and torch.equal(outs[0][k], outs[2][k])
